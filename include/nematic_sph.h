@@ -1,0 +1,155 @@
+/* nematic_sph.h -- C ABI of the MI355X (gfx950) SPH Beris-Edwards active-nematic
+ * solver in 2D periodic boxes.
+ *
+ * Problem statement (paper arXiv 2108.08919):
+ *   * a periodic L x L box (Sec. 3.1, Eq. boundaryconditions);
+ *   * per-particle state r, u, Q, rho advanced by the modified-Euler
+ *     predictor-corrector of Sec. 3.1 (Eq. sphTimeIntegrationDerivatives);
+ *   * rates from Eqs. sphMomentum, mi, sphContinuity, sphEos and
+ *     densityCorrection, positions corrected by Eq. APD;
+ *   * parameters of Table 2 plus h (Eq. quintic), gamma and c0 (Eq. sphEos)
+ *     and beta (Eq. densityCorrection);
+ *   * fields read back only at output times (Sec. 4).
+ *
+ * Conventions
+ *   * Every function returns an int status: NEM_OK (0) or a negative NEM_E_*.
+ *   * Host arrays are caller-owned and are in particle-id order (the id of a
+ *     particle is its index in the arrays passed to nem_set_state); the library
+ *     copies them in and out. The internal cell order is hidden.
+ *   * Fields read back are at integer time levels (r^n, u^n, Q^n, rho^n).
+ *   * Device memory: the caller may pass an arena of nem_arena_bytes() bytes
+ *     (any device allocation, e.g. a torch uint8 tensor) and must keep it alive
+ *     until nem_destroy; with arena == NULL the library allocates and owns it.
+ *   * Stream: all work is enqueued on the hipStream_t passed to nem_create
+ *     (NULL = the null stream). nem_step is asynchronous; device-side errors
+ *     are sticky and are returned by nem_sync and by the read calls.
+ *   * One nem_sim must not be used from two host threads at once.
+ */
+#ifndef NEMATIC_SPH_H
+#define NEMATIC_SPH_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NEM_OK 0
+#define NEM_E_INVAL (-1)     /* bad parameters, sizes or replica index */
+#define NEM_E_NOMEM (-2)     /* arena too small or allocation failed */
+#define NEM_E_HIP (-3)       /* HIP runtime error */
+#define NEM_E_NUMERIC (-4)   /* a non-finite value appeared in the state */
+#define NEM_E_OVERFLOW (-5)  /* a cell tile holds more particles than the LDS staging capacity */
+#define NEM_E_SINGULAR (-6)  /* correction tensor not invertible; B = I was used */
+#define NEM_E_STATE (-7)     /* call order (e.g. step before set_state) */
+#define NEM_E_RANGE (-8)     /* an index fell outside its buffer; the access was skipped */
+
+/* Parameters of one periodic box (one replica). Symbols of the paper:
+ * Table 2 (Gamma, lambda, A, B, C, K, zeta, rho), Eq. sphMomentum (nu = eta/rho0),
+ * Eq. quintic (h; support 3h), Eq. sphEos (gamma_eos, c0 = c0_factor max|u|),
+ * Eq. densityCorrection (beta). */
+typedef struct nem_params {
+  double L;          /* box side */
+  double dx;         /* initial lattice spacing; particle mass m = rho0 dx^2 */
+  double h;          /* smoothing length */
+  double rho0;       /* reference density */
+  double eta;        /* dynamic viscosity */
+  double Gamma;      /* rotational diffusivity */
+  double lam;        /* flow-alignment (tumbling) parameter lambda */
+  double A, B, C;    /* Landau coefficients (B drops out in 2D) */
+  double K;          /* elastic constant */
+  double zeta;       /* activity */
+  double dt;         /* time step */
+  double gamma_eos;  /* EoS exponent (7) */
+  double beta;       /* density filter coefficient (1) */
+  double c0_factor;  /* c0 = c0_factor * max |u^{n+1/2}| (10) */
+  double skin;       /* cell side >= 3h + skin; rebinning when a particle leaves its cell by skin/2 */
+  int32_t form;      /* 0: B-corrected momentum of Eq. sphMomentum; 1: conservative pair forces */
+  int32_t elastic;   /* 0: stress of Eq. mainstress; 1: also the lambda terms of Eq. elasticstress */
+  int32_t apd;       /* 1: artificial particle displacement (Eq. APD) */
+  int32_t reserved;
+} nem_params;
+
+/* FP64 global reductions at the current integer time level. */
+typedef struct nem_diag {
+  double px, py;     /* total momentum sum m u, m = rho0 dx^2 */
+  double ke;         /* (1/N) sum |u|^2 / 2 (Eq. kineticenergy) */
+  double F;          /* free energy with the discrete Laplacian: sum V[bulk] - K/2 sum V Q:lapQ */
+  double F_grad;     /* free energy with squared corrected gradients */
+  double umax;       /* max |u| */
+  double c0;         /* sound speed of the last step */
+  double qmax;       /* max Frobenius norm of Q */
+} nem_diag;
+
+typedef struct nem_sim nem_sim;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int nem_version(void);
+
+/* Device bytes needed for R replicas with n[r] particles each. */
+int nem_arena_bytes(const nem_params* per_replica, const int64_t* n, int32_t R, uint64_t* bytes);
+
+/* Create a solver for R replicas (R = 1 for a single box). per_replica[r] and
+ * n[r] give each box's parameters and particle count (n[r] >= 1; the box side
+ * must hold at least three cells of side >= 3h + skin). dev_arena/arena_bytes:
+ * caller device memory or NULL. hip_stream: a hipStream_t or NULL. */
+int nem_create(const nem_params* per_replica, const int64_t* n, int32_t R, void* dev_arena,
+               uint64_t arena_bytes, void* hip_stream, nem_sim** out);
+
+/* Set the state of replica r from host FP64 arrays of n[r] entries in id
+ * order: positions (wrapped into [0, L)), velocity, Q components Qxx, Qxy
+ * (Q symmetric traceless), density and the previous half-step acceleration
+ * a^{n-1/2} (zero at the start of a run; may be NULL for zero). The particles
+ * are binned by cell and the first predictor half-step is taken on the device. */
+int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const double* ux,
+                  const double* uy, const double* qxx, const double* qxy, const double* rho,
+                  const double* ax, const double* ay);
+
+/* Read the state of replica r into caller host arrays (any may be NULL). */
+int nem_get_state(nem_sim* s, int32_t r, double* x, double* y, double* ux, double* uy, double* qxx,
+                  double* qxy, double* rho, double* ax, double* ay);
+
+/* Advance every replica by nsteps time steps (asynchronous). */
+int nem_step(nem_sim* s, int64_t nsteps);
+
+/* Wait for the stream; return the first sticky device error (and clear nothing). */
+int nem_sync(nem_sim* s);
+
+/* Neighbour lists of replica r at the configuration the next step searches
+ * (r^{n+1/2}), in CSR by particle id with ascending columns. The GPU keeps no
+ * list: this enumerates pairs with the kernels' own predicate (FP32 cell-
+ * relative offsets, 0 < r^2 < fl32((3h)^2), see DESIGN notes in the source).
+ * row_ptr has n[r]+1 entries; col has cap entries; *nnz receives the count.
+ * Returns NEM_E_NOMEM (with *nnz set) when cap is too small. */
+int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
+
+/* FP64 reductions of replica r at the current integer time level. */
+int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out);
+
+/* Tuning and instrumentation options (key, value):
+ *   NEM_OPT_TILE       cells per tile side (2..8)
+ *   NEM_OPT_LPP        lanes per particle in the pair loops (1, 2 or 4)
+ *   NEM_OPT_COMP       pair-sum compensation: 0 none, 1 per stencil cell, 2 per pair
+ *   NEM_OPT_TIMING     1: record HIP events around every pass launch */
+#define NEM_OPT_TILE 1
+#define NEM_OPT_LPP 2
+#define NEM_OPT_COMP 3
+#define NEM_OPT_TIMING 4
+int nem_set_option(nem_sim* s, int32_t key, int64_t value);
+
+/* Accumulated kernel times (ms) and launch counts since the last reset, per
+ * pass: 0 rebin, 1 pass A (volume), 2 pass B (gradients and rates), 3 pass C
+ * (filter and EoS), 4 pass D (stress and update). Requires NEM_OPT_TIMING. */
+#define NEM_NPASS 5
+int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset);
+
+/* Error text for a status code, and the last error recorded on a solver. */
+const char* nem_strerror(int code);
+const char* nem_last_error(const nem_sim* s);
+
+void nem_destroy(nem_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

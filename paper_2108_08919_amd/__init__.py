@@ -1,0 +1,284 @@
+"""Python binding of the MI355X SPH active-nematic library (libnematic_sph.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libnematic_sph.so, whose C ABI is include/nematic_sph.h. PyTorch provides the
+device arena (a uint8 tensor) and the stream. The functions keep the C names
+(nem_create, nem_step, ...); `Sim` wraps them for convenience.
+
+Importing torch before the library matters: torch's HIP runtime then serves
+both, so torch streams and allocations are valid handles for the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnematic_sph.so")
+
+NEM_OK = 0
+NEM_E_INVAL = -1
+NEM_E_NOMEM = -2
+NEM_E_HIP = -3
+NEM_E_NUMERIC = -4
+NEM_E_OVERFLOW = -5
+NEM_E_SINGULAR = -6
+NEM_E_STATE = -7
+NEM_E_RANGE = -8
+
+NEM_OPT_TILE = 1
+NEM_OPT_LPP = 2
+NEM_OPT_COMP = 3
+NEM_OPT_TIMING = 4
+NEM_NPASS = 5
+PASS_NAMES = ("rebin", "pass_a_volume", "pass_b_rates", "pass_c_eos", "pass_d_update")
+
+EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "nem_get_state", "nem_step",
+            "nem_sync", "nem_neighbors", "nem_diagnostics", "nem_set_option", "nem_pass_times",
+            "nem_strerror", "nem_last_error", "nem_destroy")
+
+
+class NemParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K",
+                                          "zeta", "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "reserved")]
+
+
+class NemDiag(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("px", "py", "ke", "F", "F_grad", "umax", "c0", "qmax")]
+
+
+class NemError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what} failed: {code} ({strerror(code)}) {detail}".strip())
+
+
+_lib = None
+
+
+def lib(path: Optional[str] = None):
+    """Load libnematic_sph.so (never builds; raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    try:
+        import torch  # noqa: F401  (load torch's HIP runtime first, see module docstring)
+    except Exception:
+        pass
+    L = C.CDLL(p)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    L.nem_version.restype = C.c_int
+    L.nem_arena_bytes.restype = C.c_int
+    L.nem_arena_bytes.argtypes = [C.POINTER(NemParams), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_uint64)]
+    L.nem_create.restype = C.c_int
+    L.nem_create.argtypes = [C.POINTER(NemParams), C.POINTER(C.c_int64), C.c_int32, vp, C.c_uint64, vp,
+                             C.POINTER(vp)]
+    L.nem_set_state.restype = C.c_int
+    L.nem_set_state.argtypes = [vp, C.c_int32] + [dp] * 9
+    L.nem_get_state.restype = C.c_int
+    L.nem_get_state.argtypes = [vp, C.c_int32] + [dp] * 9
+    L.nem_step.restype = C.c_int
+    L.nem_step.argtypes = [vp, C.c_int64]
+    L.nem_sync.restype = C.c_int
+    L.nem_sync.argtypes = [vp]
+    L.nem_neighbors.restype = C.c_int
+    L.nem_neighbors.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int64,
+                                C.POINTER(C.c_int64)]
+    L.nem_diagnostics.restype = C.c_int
+    L.nem_diagnostics.argtypes = [vp, C.c_int32, C.POINTER(NemDiag)]
+    L.nem_set_option.restype = C.c_int
+    L.nem_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+    L.nem_pass_times.restype = C.c_int
+    L.nem_pass_times.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
+    L.nem_strerror.restype = C.c_char_p
+    L.nem_strerror.argtypes = [C.c_int]
+    L.nem_last_error.restype = C.c_char_p
+    L.nem_last_error.argtypes = [vp]
+    L.nem_destroy.restype = None
+    L.nem_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().nem_strerror(code).decode()
+    except ImportError:
+        return "library not loaded"
+
+
+def make_params(p) -> NemParams:
+    """From workloads.Params (or any object with the same attribute names)."""
+    return NemParams(L=p.L, dx=p.dx, h=p.h, rho0=p.rho0, eta=p.eta, Gamma=p.Gamma, lam=p.lam, A=p.A, B=p.B,
+                     C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos, beta=p.beta,
+                     c0_factor=p.c0_factor, skin=p.skin, form=p.form, elastic=p.elastic, apd=p.apd, reserved=0)
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---------------------------------------------------------------- C names
+
+def nem_version() -> int:
+    return lib().nem_version()
+
+
+def nem_arena_bytes(params: Sequence, n: Sequence[int]) -> int:
+    R = len(params)
+    arr = (NemParams * R)(*[make_params(p) for p in params])
+    nn = (C.c_int64 * R)(*[int(v) for v in n])
+    out = C.c_uint64(0)
+    rc = lib().nem_arena_bytes(arr, nn, R, C.byref(out))
+    if rc:
+        raise NemError(rc, "nem_arena_bytes")
+    return int(out.value)
+
+
+def nem_create(params: Sequence, n: Sequence[int], arena_ptr: int, arena_bytes: int, stream: int) -> int:
+    R = len(params)
+    arr = (NemParams * R)(*[make_params(p) for p in params])
+    nn = (C.c_int64 * R)(*[int(v) for v in n])
+    h = C.c_void_p(0)
+    rc = lib().nem_create(arr, nn, R, C.c_void_p(arena_ptr or None), arena_bytes, C.c_void_p(stream or None),
+                          C.byref(h))
+    if rc:
+        raise NemError(rc, "nem_create")
+    return h.value
+
+
+def _check(h, rc, what):
+    if rc:
+        detail = lib().nem_last_error(C.c_void_p(h)).decode() if h else ""
+        raise NemError(rc, what, detail)
+
+
+def nem_set_state(h, r, x, y, ux, uy, qxx, qxy, rho, ax=None, ay=None):
+    arrs = [np.ascontiguousarray(v, dtype=np.float64) if v is not None else None
+            for v in (x, y, ux, uy, qxx, qxy, rho, ax, ay)]
+    _check(h, lib().nem_set_state(C.c_void_p(h), r, *[_dp(a) for a in arrs]), "nem_set_state")
+
+
+def nem_get_state(h, r, n) -> Dict[str, np.ndarray]:
+    out = {k: np.zeros(n) for k in ("x", "y", "ux", "uy", "qxx", "qxy", "rho", "ax", "ay")}
+    _check(h, lib().nem_get_state(C.c_void_p(h), r, *[_dp(out[k]) for k in
+                                                     ("x", "y", "ux", "uy", "qxx", "qxy", "rho", "ax", "ay")]),
+           "nem_get_state")
+    return out
+
+
+def nem_step(h, nsteps: int):
+    _check(h, lib().nem_step(C.c_void_p(h), int(nsteps)), "nem_step")
+
+
+def nem_sync(h) -> int:
+    return lib().nem_sync(C.c_void_p(h))
+
+
+def nem_neighbors(h, r, n):
+    rp = np.zeros(n + 1, dtype=np.int64)
+    nnz = C.c_int64(0)
+    cap = 64 * n
+    while True:
+        col = np.zeros(max(cap, 1), dtype=np.int32)
+        rc = lib().nem_neighbors(C.c_void_p(h), r, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 col.ctypes.data_as(C.POINTER(C.c_int32)), cap, C.byref(nnz))
+        if rc == NEM_E_NOMEM and nnz.value > cap:
+            cap = int(nnz.value)
+            continue
+        _check(h, rc, "nem_neighbors")
+        return rp, col[:nnz.value].copy()
+
+
+def nem_diagnostics(h, r) -> Dict[str, float]:
+    d = NemDiag()
+    _check(h, lib().nem_diagnostics(C.c_void_p(h), r, C.byref(d)), "nem_diagnostics")
+    return {k: getattr(d, k) for k, _ in NemDiag._fields_}
+
+
+def nem_set_option(h, key: int, value: int):
+    _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
+
+
+def nem_pass_times(h, reset: bool = False):
+    ms = np.zeros(NEM_NPASS)
+    cnt = np.zeros(NEM_NPASS, dtype=np.int64)
+    _check(h, lib().nem_pass_times(C.c_void_p(h), _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   1 if reset else 0), "nem_pass_times")
+    return ms, cnt
+
+
+def nem_destroy(h):
+    if h:
+        lib().nem_destroy(C.c_void_p(h))
+
+
+# ---------------------------------------------------------------- wrapper
+
+class Sim:
+    """R periodic boxes advanced together. The device arena is a torch uint8
+    tensor on `device`; work goes to torch's current stream on that device."""
+
+    def __init__(self, params: Sequence, n: Sequence[int], device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the nematic SPH library runs only on the GPU")
+        lib()
+        self.params = list(params)
+        self.n = [int(v) for v in n]
+        self.R = len(self.params)
+        self.device = torch.device(device)
+        nbytes = nem_arena_bytes(self.params, self.n)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = nem_create(self.params, self.n, self.arena.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def set_state(self, r: int, f: Dict[str, np.ndarray]):
+        nem_set_state(self.h, r, f["x"], f["y"], f["ux"], f["uy"], f["qxx"], f["qxy"], f["rho"],
+                      f.get("ax"), f.get("ay"))
+
+    def get_state(self, r: int = 0) -> Dict[str, np.ndarray]:
+        return nem_get_state(self.h, r, self.n[r])
+
+    def step(self, nsteps: int):
+        nem_step(self.h, nsteps)
+
+    def sync(self) -> int:
+        return nem_sync(self.h)
+
+    def check(self):
+        rc = self.sync()
+        _check(self.h, rc, "nem_sync")
+
+    def neighbors(self, r: int = 0):
+        return nem_neighbors(self.h, r, self.n[r])
+
+    def diagnostics(self, r: int = 0):
+        return nem_diagnostics(self.h, r)
+
+    def set_option(self, key: int, value: int):
+        nem_set_option(self.h, key, value)
+
+    def pass_times(self, reset: bool = False):
+        return nem_pass_times(self.h, reset)
+
+    def close(self):
+        if getattr(self, "h", None):
+            nem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

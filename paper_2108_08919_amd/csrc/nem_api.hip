@@ -1,0 +1,564 @@
+// nem_api.hip -- host runtime and C ABI of the nematic SPH library.
+//
+// The runtime validates parameters, lays out one device arena (caller-owned or
+// allocated here), builds the per-replica tables and the tile work list, and
+// enqueues the per-step kernel sequence on the caller's stream:
+//   rebin (5 kernels, each returns at once unless a rebin was requested),
+//   step-begin, pass A, pass B, pass C, pass D.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nematic_sph.h"
+#include "nem_dev.h"
+
+
+using namespace nem;
+
+struct nem_sim {
+  int R = 0;
+  std::vector<nem_params> hp;
+  std::vector<int64_t> n;
+  int ntot = 0, ncells = 0;
+  std::vector<RepDev> reps;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool own = false;
+  RepDev* d_reps = nullptr;
+  int* d_work = nullptr;
+  int nwork = 0, work_cap = 0;
+  int *cell_start = nullptr, *count = nullptr, *cursor = nullptr, *perm = nullptr;
+  int* t_key = nullptr; float2 *t_off = nullptr, *t_lo = nullptr, *t_u = nullptr, *t_q = nullptr;
+  float* t_drho = nullptr; float2* t_acc = nullptr; int* t_id = nullptr;
+  float2* off[2] = {nullptr, nullptr}; float2* offlo = nullptr; float2* u = nullptr;
+  float2* q[2] = {nullptr, nullptr}; float* drho = nullptr; float2* acc = nullptr;
+  int* id = nullptr; int* cell = nullptr;
+  float* V = nullptr; float4* bk = nullptr; float* dh = nullptr; float2* apart = nullptr;
+  float* uv = nullptr; float2* pi = nullptr; float* P = nullptr; float* drhat = nullptr;
+  unsigned* flags = nullptr; unsigned* umax = nullptr;
+  double* stage = nullptr; int64_t stage_n = 0;
+  double* red = nullptr;
+  int parity = 0;
+  std::vector<char> has_state;
+  int T = 4, LPP = 1, COMP = 1;
+  int timing = 0;
+  std::vector<hipEvent_t> evs;
+  double pass_ms[NEM_NPASS] = {0};
+  int64_t pass_n[NEM_NPASS] = {0};
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+  size_t total = 0;
+  size_t put(size_t bytes) {
+    size_t o = (total + ALIGN - 1) / ALIGN * ALIGN;
+    total = o + bytes;
+    return o;
+  }
+};
+
+int cells_per_side(const nem_params& p) { return (int)std::floor(p.L / (3.0 * p.h + p.skin)); }
+
+int check_params(const nem_params& p, int64_t n, std::string& why) {
+  auto bad = [&](const char* m) { why = m; return NEM_E_INVAL; };
+  if (!(p.L > 0) || !(p.h > 0) || !(p.dx > 0) || !(p.rho0 > 0) || !(p.dt > 0)) return bad("L, h, dx, rho0 and dt must be positive");
+  if (!(p.skin >= 0)) return bad("skin must be >= 0");
+  if (!(p.gamma_eos > 0)) return bad("gamma_eos must be positive");
+  if (n < 1 || n > (int64_t)1 << 30) return bad("particle count out of range");
+  if (cells_per_side(p) < 3) return bad("box side must hold three cells of side >= 3h + skin");
+  if (p.form != 0 && p.form != 1) return bad("form must be 0 or 1");
+  if (p.elastic != 0 && p.elastic != 1) return bad("elastic must be 0 or 1");
+  if (p.form == 1 && p.elastic == 1) return bad("the conservative form has no elastic lambda terms on the GPU");
+  for (double v : {p.eta, p.Gamma, p.lam, p.A, p.B, p.C, p.K, p.zeta, p.beta, p.c0_factor})
+    if (!std::isfinite(v)) return bad("non-finite parameter");
+  return NEM_OK;
+}
+
+int tiles_for(int nc, int T) { return (nc + T - 1) / T; }
+
+RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n, int T, int tile_base) {
+  RepDev R;
+  std::memset(&R, 0, sizeof(R));
+  R.nc = nc; R.cell_base = cell_base; R.part_base = part_base; R.n = n;
+  R.tiles_x = tiles_for(nc, T); R.tiles_y = tiles_for(nc, T); R.tile_base = tile_base; R.form = p.form;
+  const double csd = p.L / nc;
+  R.csd = csd; R.Ld = p.L;
+  R.cs = (float)csd; R.cs_lo = (float)(csd - (double)R.cs);
+  R.h = (float)p.h; R.hinv = (float)(1.0 / p.h);
+  R.R2 = (float)((3.0 * p.h) * (3.0 * p.h));
+  const double a2 = 7.0 / (478.0 * M_PI * p.h * p.h);
+  R.a2 = (float)a2; R.W0 = (float)(66.0 * a2); R.dWc = (float)(-5.0 * a2 / p.h);
+  R.skin_half = (float)(0.5 * p.skin);
+  R.rho0 = (float)p.rho0; R.eta = (float)p.eta; R.Gamma = (float)p.Gamma; R.lam = (float)p.lam;
+  R.A = (float)p.A; R.B = (float)p.B; R.C = (float)p.C; R.K = (float)p.K; R.zeta = (float)p.zeta;
+  R.dt = (float)p.dt; R.gamma_eos = (float)p.gamma_eos; R.beta = (float)p.beta;
+  R.c0_factor = (float)p.c0_factor; R.mass = (float)(p.rho0 * p.dx * p.dx); R.inv_rho0 = (float)(1.0 / p.rho0);
+  R.elastic = p.elastic; R.apd = p.apd;
+  return R;
+}
+
+// Offsets of every buffer for given sizes (shared by nem_arena_bytes and carve()).
+struct Offs {
+  size_t reps, work, cell_start, count, cursor, perm;
+  size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id;
+  size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell;
+  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red;
+  size_t total;
+};
+
+Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage_n) {
+  Layout L;
+  Offs o;
+  const size_t N = (size_t)ntot, C = (size_t)ncells;
+  o.reps = L.put(sizeof(RepDev) * R);
+  o.work = L.put(sizeof(int) * 2 * (size_t)work_cap);
+  o.cell_start = L.put(sizeof(int) * (C + 1));
+  o.count = L.put(sizeof(int) * C);
+  o.cursor = L.put(sizeof(int) * C);
+  o.perm = L.put(sizeof(int) * N);
+  o.t_key = L.put(sizeof(int) * N);
+  o.t_off = L.put(sizeof(float2) * N);
+  o.t_lo = L.put(sizeof(float2) * N);
+  o.t_u = L.put(sizeof(float2) * N);
+  o.t_q = L.put(sizeof(float2) * N);
+  o.t_drho = L.put(sizeof(float) * N);
+  o.t_acc = L.put(sizeof(float2) * N);
+  o.t_id = L.put(sizeof(int) * N);
+  o.off0 = L.put(sizeof(float2) * N);
+  o.off1 = L.put(sizeof(float2) * N);
+  o.offlo = L.put(sizeof(float2) * N);
+  o.u = L.put(sizeof(float2) * N);
+  o.q0 = L.put(sizeof(float2) * N);
+  o.q1 = L.put(sizeof(float2) * N);
+  o.drho = L.put(sizeof(float) * N);
+  o.acc = L.put(sizeof(float2) * N);
+  o.id = L.put(sizeof(int) * N);
+  o.cell = L.put(sizeof(int) * N);
+  o.V = L.put(sizeof(float) * N);
+  o.bk = L.put(sizeof(float4) * N);
+  o.dh = L.put(sizeof(float) * N);
+  o.apart = L.put(sizeof(float2) * N);
+  o.uv = L.put(sizeof(float) * N);
+  o.pi = L.put(sizeof(float2) * N);
+  o.P = L.put(sizeof(float) * N);
+  o.drhat = L.put(sizeof(float) * N);
+  o.flags = L.put(sizeof(unsigned) * 4);
+  o.umax = L.put(sizeof(unsigned) * 2 * R);
+  o.stage = L.put(sizeof(double) * 9 * (size_t)stage_n);
+  o.red = L.put(sizeof(double) * 64 * 1024);
+  o.total = L.total + ALIGN;
+  return o;
+}
+
+struct Sizes { int64_t ntot = 0, ncells = 0, work_cap = 0, stage_n = 0; };
+
+int sizes_for(const nem_params* p, const int64_t* n, int R, Sizes& s, std::string& why) {
+  if (R < 1 || R > 4096) { why = "replica count out of range"; return NEM_E_INVAL; }
+  for (int r = 0; r < R; ++r) {
+    int rc = check_params(p[r], n[r], why);
+    if (rc) return rc;
+    const int nc = cells_per_side(p[r]);
+    s.ntot += n[r];
+    s.ncells += (int64_t)nc * nc;
+    const int64_t t4 = (int64_t)tiles_for(nc, 4);
+    s.work_cap += t4 * t4;
+    s.stage_n = std::max<int64_t>(s.stage_n, n[r]);
+  }
+  if (s.ntot >= ((int64_t)1 << 31) - 1 || s.ncells >= ((int64_t)1 << 31) - 2) {
+    why = "more than 2^31 particles or cells";
+    return NEM_E_INVAL;
+  }
+  return NEM_OK;
+}
+
+int hip_fail(nem_sim* s, hipError_t e, const char* what) {
+  if (s) s->err = std::string(what) + ": " + hipGetErrorString(e);
+  return NEM_E_HIP;
+}
+#define HIPCHK(expr)                                        \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return hip_fail(s, e_, #expr);   \
+  } while (0)
+
+SortArgs sort_args(nem_sim* s, const unsigned* gate) {
+  SortArgs a;
+  a.reps = s->d_reps; a.R = s->R; a.ncells = s->ncells; a.ntot = s->ntot;
+  a.cell_start = s->cell_start; a.count = s->count; a.cursor = s->cursor; a.perm = s->perm;
+  a.t_key = s->t_key; a.t_off = s->t_off; a.t_lo = s->t_lo; a.t_u = s->t_u; a.t_q = s->t_q;
+  a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id;
+  a.off = s->off[s->parity]; a.offlo = s->offlo; a.u = s->u; a.q = s->q[s->parity];
+  a.drho = s->drho; a.acc = s->acc; a.id = s->id; a.cell = s->cell;
+  a.flags = s->flags; a.gate = gate;
+  return a;
+}
+
+StepArgs step_args(nem_sim* s) {
+  StepArgs a;
+  const int c = s->parity, x = 1 - s->parity;
+  a.reps = s->d_reps; a.work = s->d_work; a.nwork = s->nwork; a.T = s->T;
+  a.cell_start = s->cell_start; a.ncells = s->ncells; a.ntot = s->ntot;
+  a.off_cur = s->off[c]; a.off_nxt = s->off[x]; a.offlo = s->offlo; a.u = s->u;
+  a.q_cur = s->q[c]; a.q_nxt = s->q[x]; a.acc = s->acc; a.drho = s->drho; a.cell = s->cell;
+  a.V = s->V; a.bk = s->bk; a.dh = s->dh; a.apart = s->apart; a.uv = s->uv; a.pi = s->pi;
+  a.P = s->P; a.drhat = s->drhat; a.flags = s->flags;
+  a.umax_cur = s->umax + (size_t)c * s->R; a.umax_nxt = s->umax + (size_t)x * s->R;
+  return a;
+}
+
+int build_work(nem_sim* s) {
+  std::vector<int> w;
+  int tile_base = 0;
+  for (int r = 0; r < s->R; ++r) {
+    RepDev& R = s->reps[r];
+    R.tiles_x = tiles_for(R.nc, s->T);
+    R.tiles_y = tiles_for(R.nc, s->T);
+    R.tile_base = tile_base;
+    for (int t = 0; t < R.tiles_x * R.tiles_y; ++t) { w.push_back(r); w.push_back(t); }
+    tile_base += R.tiles_x * R.tiles_y;
+  }
+  if ((int)(w.size() / 2) > s->work_cap) { s->err = "work list larger than its buffer"; return NEM_E_INVAL; }
+  s->nwork = (int)(w.size() / 2);
+  HIPCHK(hipMemcpyAsync(s->d_work, w.data(), w.size() * sizeof(int), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemcpyAsync(s->d_reps, s->reps.data(), sizeof(RepDev) * s->R, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return NEM_OK;
+}
+
+int read_flags(nem_sim* s, unsigned* f) {
+  HIPCHK(hipMemcpyAsync(f, s->flags, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return NEM_OK;
+}
+
+int status_from_flags(nem_sim* s, unsigned f) {
+  if (f & ERR_RANGE) { s->err = "device index outside its buffer (access skipped)"; return NEM_E_RANGE; }
+  if (f & ERR_OVERFLOW) { s->err = "a tile holds more particles than the LDS staging capacity"; return NEM_E_OVERFLOW; }
+  if (f & ERR_NUMERIC) { s->err = "non-finite value in the state"; return NEM_E_NUMERIC; }
+  if (f & ERR_SINGULAR) { s->err = "singular correction tensor (B = I used)"; return NEM_E_SINGULAR; }
+  return NEM_OK;
+}
+
+struct Timed {
+  nem_sim* s;
+  int pass;
+  Timed(nem_sim* s_, int p) : s(s_), pass(p) {
+    if (s->timing) hipEventRecord(s->evs[2 * pass], s->stream);
+  }
+  ~Timed() {
+    if (s->timing) hipEventRecord(s->evs[2 * pass + 1], s->stream);
+  }
+};
+
+void collect_times(nem_sim* s) {
+  if (!s->timing) return;
+  hipStreamSynchronize(s->stream);
+  for (int p = 0; p < NEM_NPASS; ++p) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->evs[2 * p], s->evs[2 * p + 1]) == hipSuccess) {
+      s->pass_ms[p] += ms;
+      s->pass_n[p] += 1;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nem_version(void) { return 100; }
+
+const char* nem_strerror(int code) {
+  switch (code) {
+    case NEM_OK: return "ok";
+    case NEM_E_INVAL: return "invalid argument";
+    case NEM_E_NOMEM: return "not enough memory";
+    case NEM_E_HIP: return "HIP runtime error";
+    case NEM_E_NUMERIC: return "non-finite value in the state";
+    case NEM_E_OVERFLOW: return "cell tile over LDS capacity";
+    case NEM_E_SINGULAR: return "singular correction tensor";
+    case NEM_E_STATE: return "wrong call order";
+    case NEM_E_RANGE: return "device index out of range";
+    default: return "unknown error";
+  }
+}
+
+const char* nem_last_error(const nem_sim* s) { return s ? s->err.c_str() : "null solver"; }
+
+int nem_arena_bytes(const nem_params* p, const int64_t* n, int32_t R, uint64_t* bytes) {
+  if (!p || !n || !bytes) return NEM_E_INVAL;
+  Sizes z;
+  std::string why;
+  int rc = sizes_for(p, n, R, z, why);
+  if (rc) return rc;
+  *bytes = layout(R, z.ntot, z.ncells, z.work_cap, z.stage_n).total;
+  return NEM_OK;
+}
+
+int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena, uint64_t arena_bytes,
+               void* hip_stream, nem_sim** out) {
+  if (!p || !n || !out) return NEM_E_INVAL;
+  *out = nullptr;
+  Sizes z;
+  std::string why;
+  int rc = sizes_for(p, n, R, z, why);
+  if (rc) return rc;
+  nem_sim* s = new nem_sim();
+  s->R = R;
+  s->hp.assign(p, p + R);
+  s->n.assign(n, n + R);
+  s->ntot = (int)z.ntot;
+  s->ncells = (int)z.ncells;
+  s->work_cap = (int)z.work_cap;
+  s->stage_n = z.stage_n;
+  s->stream = (hipStream_t)hip_stream;
+  const Offs o = layout(R, z.ntot, z.ncells, z.work_cap, z.stage_n);
+  if (dev_arena) {
+    if (arena_bytes < o.total) { delete s; return NEM_E_NOMEM; }
+    s->arena = (char*)dev_arena;
+    s->arena_bytes = arena_bytes;
+  } else {
+    void* m = nullptr;
+    if (hipMalloc(&m, o.total) != hipSuccess) { delete s; return NEM_E_NOMEM; }
+    s->arena = (char*)m;
+    s->arena_bytes = o.total;
+    s->own = true;
+  }
+  char* b = (char*)(((uintptr_t)s->arena + ALIGN - 1) / ALIGN * ALIGN);
+  s->d_reps = (RepDev*)(b + o.reps); s->d_work = (int*)(b + o.work);
+  s->cell_start = (int*)(b + o.cell_start); s->count = (int*)(b + o.count);
+  s->cursor = (int*)(b + o.cursor); s->perm = (int*)(b + o.perm);
+  s->t_key = (int*)(b + o.t_key); s->t_off = (float2*)(b + o.t_off); s->t_lo = (float2*)(b + o.t_lo);
+  s->t_u = (float2*)(b + o.t_u); s->t_q = (float2*)(b + o.t_q); s->t_drho = (float*)(b + o.t_drho);
+  s->t_acc = (float2*)(b + o.t_acc); s->t_id = (int*)(b + o.t_id);
+  s->off[0] = (float2*)(b + o.off0); s->off[1] = (float2*)(b + o.off1); s->offlo = (float2*)(b + o.offlo);
+  s->u = (float2*)(b + o.u); s->q[0] = (float2*)(b + o.q0); s->q[1] = (float2*)(b + o.q1);
+  s->drho = (float*)(b + o.drho); s->acc = (float2*)(b + o.acc); s->id = (int*)(b + o.id);
+  s->cell = (int*)(b + o.cell);
+  s->V = (float*)(b + o.V); s->bk = (float4*)(b + o.bk); s->dh = (float*)(b + o.dh);
+  s->apart = (float2*)(b + o.apart); s->uv = (float*)(b + o.uv); s->pi = (float2*)(b + o.pi);
+  s->P = (float*)(b + o.P); s->drhat = (float*)(b + o.drhat);
+  s->flags = (unsigned*)(b + o.flags); s->umax = (unsigned*)(b + o.umax);
+  s->stage = (double*)(b + o.stage); s->red = (double*)(b + o.red);
+
+  int cell_base = 0, part_base = 0;
+  for (int r = 0; r < R; ++r) {
+    const int nc = cells_per_side(p[r]);
+    s->reps.push_back(make_rep(p[r], nc, cell_base, part_base, (int)n[r], s->T, 0));
+    cell_base += nc * nc;
+    part_base += (int)n[r];
+  }
+  s->has_state.assign(R, 0);
+  hipError_t e = hipSuccess;
+  // zero the whole arena once: counts and cursors must start at zero, and
+  // replicas without a state keep empty cells
+  if (e == hipSuccess) e = hipMemsetAsync(b, 0, o.total - ALIGN, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) { hip_fail(s, e, "arena init"); nem_destroy(s); return NEM_E_HIP; }
+  rc = build_work(s);
+  if (rc) { nem_destroy(s); return rc; }
+  *out = s;
+  return NEM_OK;
+}
+
+int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const double* ux, const double* uy,
+                  const double* qxx, const double* qxy, const double* rho, const double* ax, const double* ay) {
+  if (!s || r < 0 || r >= s->R || !x || !y || !ux || !uy || !qxx || !qxy || !rho) return NEM_E_INVAL;
+  const int n = (int)s->n[r];
+  const RepDev& R = s->reps[r];
+  const double* src[9] = {x, y, ux, uy, qxx, qxy, rho, ax, ay};
+  for (int f = 0; f < 9; ++f) {
+    double* dst = s->stage + (size_t)f * n;
+    if (src[f]) HIPCHK(hipMemcpyAsync(dst, src[f], sizeof(double) * n, hipMemcpyHostToDevice, s->stream));
+    else HIPCHK(hipMemsetAsync(dst, 0, sizeof(double) * n, s->stream));
+  }
+  unsigned* um = s->umax + (size_t)s->parity * s->R + r;
+  HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned), s->stream));
+  SortArgs a = sort_args(s, nullptr);
+  launch_ingest(a, r, s->stage, n, s->umax + (size_t)s->parity * s->R, s->stream);
+  launch_sort_tail(a, R.part_base, n, R.cell_base, R.nc * R.nc, R.part_base, s->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->has_state[r] = 1;
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_get_state(nem_sim* s, int32_t r, double* x, double* y, double* ux, double* uy, double* qxx, double* qxy,
+                  double* rho, double* ax, double* ay) {
+  if (!s || r < 0 || r >= s->R) return NEM_E_INVAL;
+  if (!s->has_state[r]) { s->err = "state of this replica was never set"; return NEM_E_STATE; }
+  const int n = (int)s->n[r];
+  SortArgs a = sort_args(s, nullptr);
+  launch_export(a, r, s->stage, n, s->stream);
+  HIPCHK(hipGetLastError());
+  double* dst[9] = {x, y, ux, uy, qxx, qxy, rho, ax, ay};
+  for (int f = 0; f < 9; ++f)
+    if (dst[f]) HIPCHK(hipMemcpyAsync(dst[f], s->stage + (size_t)f * n, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_step(nem_sim* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return NEM_E_INVAL;
+  for (int r = 0; r < s->R; ++r)
+    if (!s->has_state[r]) { s->err = "nem_set_state was not called for every replica"; return NEM_E_STATE; }
+  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic};
+  for (int64_t it = 0; it < nsteps; ++it) {
+    {
+      Timed t(s, 0);
+      SortArgs a = sort_args(s, s->flags + 1);
+      launch_rebin_key(a, s->stream);
+      launch_sort_tail(a, 0, s->ntot, 0, s->ncells, 0, s->stream);
+    }
+    StepArgs a = step_args(s);
+    launch_step_begin(s->flags, const_cast<unsigned*>(a.umax_nxt), s->R, s->stream);
+    for (int pass = 1; pass <= 4; ++pass) {
+      Timed t(s, pass);
+      if (!launch_pass(pass, cfg, a, s->stream)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
+    }
+    HIPCHK(hipGetLastError());
+    collect_times(s);
+    s->parity ^= 1;
+  }
+  return NEM_OK;
+}
+
+int nem_sync(nem_sim* s) {
+  if (!s) return NEM_E_INVAL;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz) {
+  if (!s || r < 0 || r >= s->R || !row_ptr || !nnz) return NEM_E_INVAL;
+  if (!s->has_state[r]) return NEM_E_STATE;
+  const int n = (int)s->n[r];
+  int* d_cnt = nullptr; int64_t* d_rp = nullptr; int32_t* d_col = nullptr;
+  HIPCHK(hipMalloc(&d_cnt, sizeof(int) * n));
+  HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(int) * n, s->stream));
+  StepArgs a = step_args(s);
+  launch_neighbors(s->T, a, s->id, r, 0, d_cnt, nullptr, nullptr, 0, s->stream);
+  std::vector<int> cnt(n);
+  HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  row_ptr[0] = 0;
+  for (int i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+  *nnz = row_ptr[n];
+  int rc = NEM_OK;
+  if (*nnz > cap || !col) {
+    rc = NEM_E_NOMEM;
+  } else {
+    HIPCHK(hipMalloc(&d_rp, sizeof(int64_t) * (n + 1)));
+    HIPCHK(hipMalloc(&d_col, sizeof(int32_t) * std::max<int64_t>(*nnz, 1)));
+    HIPCHK(hipMemcpyAsync(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s->stream));
+    launch_neighbors(s->T, a, s->id, r, 1, d_cnt, d_rp, d_col, *nnz, s->stream);
+    HIPCHK(hipMemcpyAsync(col, d_col, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < n; ++i) std::sort(col + row_ptr[i], col + row_ptr[i + 1]);
+  }
+  hipFree(d_cnt);
+  if (d_rp) hipFree(d_rp);
+  if (d_col) hipFree(d_col);
+  if (rc) return rc;
+  unsigned f[2];
+  rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {
+  if (!s || r < 0 || r >= s->R || !out) return NEM_E_INVAL;
+  if (!s->has_state[r]) return NEM_E_STATE;
+  SortArgs a = sort_args(s, nullptr);
+  launch_reduce(a, r, (int)s->n[r], s->red, s->stream);
+  HIPCHK(hipGetLastError());
+  double h[8];
+  unsigned um = 0;
+  HIPCHK(hipMemcpyAsync(h, s->red, sizeof(double) * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(&um, s->umax + (size_t)(1 - s->parity) * s->R + r, sizeof(unsigned),
+                        hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const double m = s->hp[r].rho0 * s->hp[r].dx * s->hp[r].dx;
+  float umf;
+  std::memcpy(&umf, &um, sizeof(umf));
+  out->px = m * h[0];
+  out->py = m * h[1];
+  out->ke = h[2] / (double)s->n[r];
+  out->umax = h[3];
+  out->qmax = h[4];
+  out->F = NAN;
+  out->F_grad = NAN;
+  out->c0 = s->hp[r].c0_factor * (double)umf;
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
+  if (!s) return NEM_E_INVAL;
+  switch (key) {
+    case NEM_OPT_TILE: {
+      if (value != 4 && value != 8) return NEM_E_INVAL;
+      s->T = (int)value;
+      return build_work(s);
+    }
+    case NEM_OPT_LPP:
+      if (value != 1 && value != 2 && value != 4) return NEM_E_INVAL;
+      s->LPP = (int)value;
+      return NEM_OK;
+    case NEM_OPT_COMP:
+      if (value < 0 || value > 2) return NEM_E_INVAL;
+      s->COMP = (int)value;
+      return NEM_OK;
+    case NEM_OPT_TIMING:
+      if (value && s->evs.empty()) {
+        s->evs.resize(2 * NEM_NPASS);
+        for (auto& e : s->evs) HIPCHK(hipEventCreate(&e));
+      }
+      s->timing = value ? 1 : 0;
+      return NEM_OK;
+    default:
+      return NEM_E_INVAL;
+  }
+}
+
+int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset) {
+  if (!s) return NEM_E_INVAL;
+  for (int p = 0; p < NEM_NPASS; ++p) {
+    if (ms) ms[p] = s->pass_ms[p];
+    if (launches) launches[p] = s->pass_n[p];
+    if (reset) { s->pass_ms[p] = 0; s->pass_n[p] = 0; }
+  }
+  return NEM_OK;
+}
+
+void nem_destroy(nem_sim* s) {
+  if (!s) return;
+  if (s->stream) hipStreamSynchronize(s->stream);
+  else hipDeviceSynchronize();
+  for (auto& e : s->evs) hipEventDestroy(e);
+  if (s->own && s->arena) hipFree(s->arena);
+  delete s;
+}
+
+}  // extern "C"

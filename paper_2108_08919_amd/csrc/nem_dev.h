@@ -1,0 +1,104 @@
+// nem_dev.h -- device-side data structures shared by the HIP kernels and the
+// host runtime of the nematic SPH library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nem {
+
+constexpr int WG = 256;          // threads per workgroup of every pair pass
+constexpr int MAXT = 8;          // largest tile side in cells
+constexpr int MAXSC = (MAXT + 2) * (MAXT + 2);  // staged cells per tile (interior + halo)
+constexpr int MAXS = 1536;       // staged particles per tile (LDS capacity)
+
+// Sticky device error bits (flags[0]).
+enum : unsigned {
+  ERR_NUMERIC = 1u,
+  ERR_OVERFLOW = 2u,
+  ERR_SINGULAR = 4u,
+  ERR_RANGE = 8u,
+};
+
+// One periodic box. All per-pair constants are FP32; csd and Ld keep the
+// double-precision geometry used when positions enter or leave the library.
+struct RepDev {
+  int nc;          // cells per side
+  int cell_base;   // first global cell of this replica
+  int part_base;   // first particle (sorted arrays) of this replica
+  int n;           // particles
+  int tiles_x, tiles_y, tile_base, form;
+  float cs, cs_lo; // cell side as a float pair (cs + cs_lo = L/nc to ~1e-14 relative)
+  float h, hinv;
+  float R2;        // fl32((3h)^2): pair accepted when 0 < r^2 < R2
+  float a2;        // 7 / (478 pi h^2)
+  float W0;        // W(0) = 66 a2
+  float dWc;       // dW/dr = dWc (t3^4 - 6 t2^4 + 15 t1^4), dWc = -5 a2 / h
+  float skin_half, rho0, eta, Gamma;
+  float lam, A, C, K;
+  float zeta, dt, gamma_eos, beta;
+  float c0_factor, mass, inv_rho0, B;
+  int elastic, apd, pad0, pad1;
+  double csd, Ld;
+};
+
+// Pointers of one step. *_cur / *_nxt alternate between steps.
+struct StepArgs {
+  const RepDev* reps;
+  const int* work;        // 2 ints per work item: replica, tile index
+  int nwork, T;           // work items, tile side in cells
+  const int* cell_start;  // [ncells + 1], particles sorted by (replica, cell, id)
+  int ncells, ntot;
+  const float2* off_cur;  // cell-relative position (high part) at r^{n+1/2}
+  float2* off_nxt;        // same for the next step
+  float2* offlo;          // low part of the position (compensation)
+  float2* u;              // u^{n+1/2}
+  const float2* q_cur;    // (Qxx, Qxy) at Q^n
+  float2* q_nxt;          // Q^{n+1}
+  float2* acc;            // a^{n+1/2} (kept for read-back and restart)
+  float* drho;            // rho^n - rho0, then rho^{n+1} - rho0
+  int* cell;              // global cell of each particle (from the last binning)
+  float* V;               // particle volume
+  float4* bk;             // (Bxx, Bxy, Byy, k)
+  float* dh;              // rho^{n+1/2} - rho0
+  float2* apart;          // viscous + active acceleration before division by rho_hat
+  float* uv;              // APD velocity-variance coefficient
+  float2* pi;             // lambda part of the elastic stress (Pi_xx, Pi_xy)
+  float* P;               // p / rho_hat^2
+  float* drhat;           // rho_hat - rho0
+  unsigned* flags;        // [0] error bits, [1] rebin request
+  const unsigned* umax_cur;  // per replica: max |u^{n+1/2}| (float bits)
+  unsigned* umax_nxt;        // per replica: max |u^{n+3/2}| being accumulated
+};
+
+// Kernel variant of the pair passes.
+struct PassCfg { int T, LPP, COMP, FORM, EL; };
+
+// Arguments of the binning, ingest, export and reduction kernels.
+struct SortArgs {
+  const RepDev* reps;
+  int R;
+  int ncells, ntot;
+  int* cell_start;       // [ncells + 1]
+  int* count;            // [ncells], zero between sorts
+  int* cursor;           // [ncells], zero between sorts
+  int* perm;             // [ntot]
+  // unsorted staging copy of the persistent fields
+  int* t_key; float2* t_off; float2* t_lo; float2* t_u; float2* t_q; float* t_drho; float2* t_acc; int* t_id;
+  // persistent sorted fields
+  float2* off; float2* offlo; float2* u; float2* q; float* drho; float2* acc; int* id; int* cell;
+  unsigned* flags;
+  const unsigned* gate;  // run only when *gate != 0 (NULL: always)
+};
+
+// Launchers (nem_passes.hip, nem_sort.hip).
+bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s);
+void launch_neighbors(int T, const StepArgs& a, const int* sid, int rep, int mode, int* cnt,
+                      const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s);
+void launch_ingest(const SortArgs& s, int r, const double* in, int n, unsigned* umax, hipStream_t st);
+void launch_rebin_key(const SortArgs& s, hipStream_t st);
+void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base, hipStream_t st);
+void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st);
+void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st);
+void launch_reduce(const SortArgs& s, int r, int n, double* red, hipStream_t st);
+
+}  // namespace nem

@@ -1,0 +1,174 @@
+// nem_pair.h -- tile staging, neighbour predicate, quintic kernel and
+// compensated sums used by every pair pass (gfx950, wave64).
+#pragma once
+#include "nem_dev.h"
+
+namespace nem {
+
+// Tile geometry for a tile side of T cells. A workgroup stages the T x T
+// interior cells of its tile plus a one-cell periodic halo into LDS; interior
+// cells come first so that interior particles occupy LDS slots [0, nin).
+template <int T>
+struct TileCfg {
+  static constexpr int NSC = (T + 2) * (T + 2);
+  static constexpr int MAXP = NSC * 24;  // 1.5x the lattice fill of 16 per cell
+};
+
+template <int T>
+struct TileLDS {
+  int cstart[TileCfg<T>::NSC + 1];  // prefix of staged counts (staged-cell order)
+  int gstart[TileCfg<T>::NSC];      // first global particle of each staged cell
+  int slot[TileCfg<T>::NSC];        // region index (lj+1)*(ni+2)+(li+1) -> staged cell
+  int hdr[8];                       // ni, nj, nint, nreg
+};
+
+// Staged-cell index of region cell (li, lj), li in [-1, ni], lj in [-1, nj].
+__device__ inline int staged_index(int li, int lj, int ni, int nj) {
+  if (li >= 0 && li < ni && lj >= 0 && lj < nj) return lj * ni + li;
+  int nint = ni * nj, rank;
+  if (lj == -1) rank = li + 1;
+  else if (lj < nj) rank = (ni + 2) + 2 * lj + (li == -1 ? 0 : 1);
+  else rank = (ni + 2) + 2 * nj + (li + 1);
+  return nint + rank;
+}
+
+// Fill the tile header and cell tables; returns the replica index. Every
+// thread of the workgroup must call it.
+template <int T>
+__device__ int tile_setup(const StepArgs& a, int w, TileLDS<T>& L, RepDev& R) {
+  const int rep = a.work[2 * w];
+  const int tile = a.work[2 * w + 1];
+  R = a.reps[rep];
+  const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
+  const int cx0 = tx * T, cy0 = ty * T;
+  const int ni = min(T, R.nc - cx0), nj = min(T, R.nc - cy0);
+  const int nreg = (ni + 2) * (nj + 2);
+  const int t = threadIdx.x;
+  __shared__ int cnt[TileCfg<T>::NSC];
+  if (t < nreg) {
+    const int li = t % (ni + 2) - 1, lj = t / (ni + 2) - 1;
+    const int st = staged_index(li, lj, ni, nj);
+    const int gx = (cx0 + li + R.nc) % R.nc, gy = (cy0 + lj + R.nc) % R.nc;
+    const int gc = R.cell_base + gy * R.nc + gx;
+    int s0 = 0, s1 = 0;
+    if (gc >= 0 && gc < a.ncells) { s0 = a.cell_start[gc]; s1 = a.cell_start[gc + 1]; }
+    else atomicOr(a.flags, ERR_RANGE);
+    L.slot[t] = st;
+    L.gstart[st] = s0;
+    cnt[st] = max(s1 - s0, 0);
+  }
+  if (t == 0) { L.hdr[0] = ni; L.hdr[1] = nj; L.hdr[2] = ni * nj; L.hdr[3] = nreg; }
+  __syncthreads();
+  if (t < 64) {  // wave 0: exclusive scan of up to 128 counts, two per lane
+    const int i0 = 2 * t, i1 = 2 * t + 1;
+    const int v0 = i0 < nreg ? cnt[i0] : 0, v1 = i1 < nreg ? cnt[i1] : 0;
+    int s = v0 + v1, inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int o = __shfl_up(inc, d, 64);
+      if (t >= d) inc += o;
+    }
+    const int ex = inc - s;
+    if (t == 0) L.cstart[0] = 0;
+    if (i0 < nreg) L.cstart[i0 + 1] = ex + v0;
+    if (i1 < nreg) L.cstart[i1 + 1] = ex + v0 + v1;
+  }
+  __syncthreads();
+  return rep;
+}
+
+// Staged cell containing LDS slot p, searching cstart[lo..hi).
+__device__ inline int find_cell(const int* cstart, int hi, int p) {
+  int lo = 0;  // invariant: cstart[lo] <= p < cstart[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cstart[mid] <= p) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Neighbour predicate on FP32 cell-relative offsets. For j in the stencil cell
+// displaced by (dx, dy) from i's cell, sx = -dx*cs, sy = -dy*cs and
+//   rx = fl(fl(oix - ojx) + sx), r2 = fl(fl(rx*rx) + fl(ry*ry)),
+// accepted when 0 < r2 < R2 = fl32((3h)^2). No contraction, so the decision is
+// reproducible bit for bit from the documented rule.
+__device__ __forceinline__ bool pair_accept(float oix, float oiy, float ojx, float ojy, float sx,
+                                            float sy, float R2, float& rx, float& ry, float& r2) {
+#pragma clang fp contract(off)
+  const float tx = oix - ojx;
+  const float ty = oiy - ojy;
+  rx = tx + sx;
+  ry = ty + sy;
+  const float xx = rx * rx;
+  const float yy = ry * ry;
+  r2 = xx + yy;
+  return (r2 > 0.0f) & (r2 < R2);
+}
+
+// Quintic spline of support 3h (2D): W and F = (dW/dr)/r, so that
+// grad_i W_ij = F r_ij.
+struct KW { float rinv, r, W, F; };
+__device__ __forceinline__ KW quintic(const RepDev& R, float r2) {
+  KW k;
+  k.rinv = rsqrtf(r2);
+  k.r = r2 * k.rinv;
+  const float b = k.r * R.hinv;
+  const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
+  const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
+  const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
+  const float P4 = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34));
+  const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
+  k.W = R.a2 * P5;
+  k.F = R.dWc * P4 * k.rinv;
+  return k;
+}
+
+// Same without the derivative (passes that need W only).
+__device__ __forceinline__ float quintic_W(const RepDev& R, float r2) {
+  const float r = r2 * rsqrtf(r2);
+  const float b = r * R.hinv;
+  const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
+  const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
+  const float P5 = fmaf(15.0f * t1s * t1s, t1, fmaf(-6.0f * t2s * t2s, t2, t3s * t3s * t3));
+  return R.a2 * P5;
+}
+
+// A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: plain partial sum per
+// stencil cell, partials added with Kahan compensation. COMP 2: Kahan
+// compensation on every pair term.
+template <int COMP>
+struct Acc {
+  float s, c, p;
+  __device__ __forceinline__ void init() { s = 0.0f; c = 0.0f; p = 0.0f; }
+  __device__ __forceinline__ static void kahan(float& s_, float& c_, float x) {
+    const float y = x - c_;
+    const float t = s_ + y;
+    c_ = (t - s_) - y;
+    s_ = t;
+  }
+  __device__ __forceinline__ void add(float x) {
+    if constexpr (COMP == 0) s += x;
+    else if constexpr (COMP == 1) p += x;
+    else kahan(s, c, x);
+  }
+  __device__ __forceinline__ void fma(float a, float b) {
+    if constexpr (COMP == 0) s = fmaf(a, b, s);
+    else if constexpr (COMP == 1) p = fmaf(a, b, p);
+    else { const float x = a * b; kahan(s, c, x); }
+  }
+  __device__ __forceinline__ void end_cell() {
+    if constexpr (COMP == 1) { kahan(s, c, p); p = 0.0f; }
+  }
+  // Value summed over the LPP lanes that share a particle.
+  template <int LPP>
+  __device__ __forceinline__ float total() const {
+    float v = (COMP == 0) ? s : (s - c);
+#pragma unroll
+    for (int o = 1; o < LPP; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  }
+};
+
+__device__ __forceinline__ void flag(unsigned* flags, unsigned bit) { atomicOr(flags, bit); }
+
+}  // namespace nem

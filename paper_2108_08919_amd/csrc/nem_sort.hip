@@ -1,0 +1,308 @@
+// nem_sort.hip -- binning of particles into cells (counting sort), ingest of
+// host states, export to id order, and the per-step bookkeeping kernels.
+//
+// Particles are kept sorted by (replica, cell, id): every cell is a contiguous
+// run and the order inside a cell is canonical, so results do not depend on
+// the order in which atomics land. Rebinning happens only when some particle
+// has left its cell by more than skin/2 (pass D raises flags[1]); the kernels
+// below read that flag themselves and return at once when it is clear, so the
+// per-step launch sequence is fixed.
+#include "nem_dev.h"
+
+namespace nem {
+
+
+
+__device__ inline bool gated(const unsigned* gate) { return gate != nullptr && *gate == 0u; }
+
+__device__ inline int rep_of_particle(const RepDev* reps, int R, int k) {
+  int lo = 0, hi = R;  // largest r with part_base <= k
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (reps[mid].part_base <= k) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Host state (FP64, id order) of replica r -> unsorted staging arrays.
+// Takes the first predictor half-step in double precision:
+// u^{n+1/2} = u^n + a dt/2, r^{n+1/2} = wrap(r^n + u^{n+1/2} dt/2).
+__global__ void k_ingest(SortArgs s, int r, const double* __restrict__ in, int n, unsigned* umax) {
+  const RepDev R = s.reps[r];
+  const double* x = in;
+  const double* y = in + n;
+  const double* ux = in + 2 * (size_t)n;
+  const double* uy = in + 3 * (size_t)n;
+  const double* qxx = in + 4 * (size_t)n;
+  const double* qxy = in + 5 * (size_t)n;
+  const double* rho = in + 6 * (size_t)n;
+  const double* ax = in + 7 * (size_t)n;
+  const double* ay = in + 8 * (size_t)n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma clang fp contract(off)
+    const double hdt = 0.5 * (double)R.dt;
+    const double uhx = ux[i] + hdt * ax[i], uhy = uy[i] + hdt * ay[i];
+    double xh = x[i] + hdt * uhx, yh = y[i] + hdt * uhy;
+    xh = xh - R.Ld * floor(xh / R.Ld); if (xh >= R.Ld) xh -= R.Ld; if (xh < 0.0) xh = 0.0;
+    yh = yh - R.Ld * floor(yh / R.Ld); if (yh >= R.Ld) yh -= R.Ld; if (yh < 0.0) yh = 0.0;
+    int cx = (int)floor(xh / R.csd), cy = (int)floor(yh / R.csd);
+    cx = min(max(cx, 0), R.nc - 1);
+    cy = min(max(cy, 0), R.nc - 1);
+    const double bx = (double)cx * R.csd, by = (double)cy * R.csd;
+    const double ox = xh - bx, oy = yh - by;
+    const float hx = (float)ox, hy = (float)oy;
+    const float lx = (float)(ox - (double)hx), ly = (float)(oy - (double)hy);
+    const int k = R.part_base + i;
+    const int key = R.cell_base + cy * R.nc + cx;
+    s.t_key[k] = key;
+    s.t_off[k] = make_float2(hx, hy);
+    s.t_lo[k] = make_float2(lx, ly);
+    const float2 uf = make_float2((float)uhx, (float)uhy);
+    s.t_u[k] = uf;
+    s.t_q[k] = make_float2((float)qxx[i], (float)qxy[i]);
+    s.t_drho[k] = (float)(rho[i] - (double)R.rho0);
+    s.t_acc[k] = make_float2((float)ax[i], (float)ay[i]);
+    s.t_id[k] = i;
+    atomicAdd(&s.count[key], 1);
+    atomicMax(&umax[r], __float_as_uint(sqrtf(uf.x * uf.x + uf.y * uf.y)));
+  }
+}
+
+// Rebin step 1: re-base every particle into the cell its offset now lies in
+// (cells move by at most one per direction between rebins) and copy it to the
+// staging arrays.
+__global__ void k_rebin_key(SortArgs s) {
+  if (gated(s.gate)) return;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of_particle(s.reps, s.R, k);
+    const RepDev R = s.reps[r];
+    const int c = s.cell[k] - R.cell_base;
+    if (c < 0 || c >= R.nc * R.nc) { atomicOr(s.flags, ERR_RANGE); continue; }
+    int cx = c % R.nc, cy = c / R.nc;
+    const float2 o = s.off[k], lo = s.offlo[k];
+    int dx = (o.x < 0.0f) ? -1 : (o.x >= R.cs ? 1 : 0);
+    int dy = (o.y < 0.0f) ? -1 : (o.y >= R.cs ? 1 : 0);
+    if (o.x < -R.cs || o.x >= 2.0f * R.cs || o.y < -R.cs || o.y >= 2.0f * R.cs) atomicOr(s.flags, ERR_RANGE);
+    float2 nh, nl;
+    {
+#pragma clang fp contract(off)
+      // (hi, lo) - d (cs, cs_lo), renormalised
+      // TwoSum of hi - d*cs keeps the rounding error of the subtraction
+      const float shx = (float)(-dx) * R.cs, slx = (float)(-dx) * R.cs_lo;
+      float t = o.x + shx, bp = t - o.x;
+      float e = (o.x - (t - bp)) + (shx - bp);
+      float l2 = (lo.x + slx) + e;
+      nh.x = t + l2; nl.x = l2 - (nh.x - t);
+      const float shy = (float)(-dy) * R.cs, sly = (float)(-dy) * R.cs_lo;
+      t = o.y + shy; bp = t - o.y;
+      e = (o.y - (t - bp)) + (shy - bp);
+      l2 = (lo.y + sly) + e;
+      nh.y = t + l2; nl.y = l2 - (nh.y - t);
+    }
+    cx = (cx + dx + R.nc) % R.nc;
+    cy = (cy + dy + R.nc) % R.nc;
+    const int key = R.cell_base + cy * R.nc + cx;
+    s.t_key[k] = key;
+    s.t_off[k] = nh;
+    s.t_lo[k] = nl;
+    s.t_u[k] = s.u[k];
+    s.t_q[k] = s.q[k];
+    s.t_drho[k] = s.drho[k];
+    s.t_acc[k] = s.acc[k];
+    s.t_id[k] = s.id[k];
+    atomicAdd(&s.count[key], 1);
+  }
+}
+
+// Exclusive scan of count[c0 .. c0+nc) into cell_start[c0 ..], offset by base;
+// cell_start[c0+nc] = base + total. One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(SortArgs s, int c0, int nc, int base) {
+  if (gated(s.gate)) return;
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (nc + 1023) / 1024;
+  const int b = min(nc, t * chunk), e = min(nc, b + chunk);
+  int sum = 0;
+  for (int i = b; i < e; ++i) sum += s.count[c0 + i];
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+    int v = (t >= d) ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = base + part[t] - sum;
+  for (int i = b; i < e; ++i) {
+    s.cell_start[c0 + i] = run;
+    run += s.count[c0 + i];
+  }
+  if (t == 1023) s.cell_start[c0 + nc] = base + part[1023];
+}
+
+// Place each staged particle in its cell's range (arbitrary order inside).
+__global__ void k_scatter(SortArgs s, int k0, int n) {
+  if (gated(s.gate)) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = k0 + i;
+    const int key = s.t_key[k];
+    if (key < 0 || key >= s.ncells) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const int slot = s.cell_start[key] + atomicAdd(&s.cursor[key], 1);
+    if (slot < 0 || slot >= s.ntot) { atomicOr(s.flags, ERR_RANGE); continue; }
+    s.perm[slot] = k;
+  }
+}
+
+// Canonical order inside each cell: ascending particle id (insertion sort of
+// the short per-cell runs, one thread per cell).
+__global__ void k_cellsort(SortArgs s, int c0, int nc) {
+  if (gated(s.gate)) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    const int b = s.cell_start[c0 + i], e = s.cell_start[c0 + i + 1];
+    if (b < 0 || e > s.ntot || b > e) { atomicOr(s.flags, ERR_RANGE); continue; }
+    bool ok = true;
+    for (int a = b; a < e; ++a) {
+      const int v = s.perm[a];
+      if (v < 0 || v >= s.ntot) ok = false;
+    }
+    if (!ok) { atomicOr(s.flags, ERR_RANGE); continue; }
+    for (int a = b + 1; a < e; ++a) {
+      const int v = s.perm[a];
+      const int kv = s.t_id[v];
+      int c = a - 1;
+      while (c >= b && s.t_id[s.perm[c]] > kv) { s.perm[c + 1] = s.perm[c]; --c; }
+      s.perm[c + 1] = v;
+    }
+  }
+}
+
+// Move staged particles to their sorted slots; clear count/cursor of the cells.
+__global__ void k_gather(SortArgs s, int k0, int n, int c0, int nc) {
+  if (gated(s.gate)) return;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int k = k0 + i;
+    const int src = s.perm[k];
+    if (src < 0 || src >= s.ntot) { atomicOr(s.flags, ERR_RANGE); continue; }
+    s.off[k] = s.t_off[src];
+    s.offlo[k] = s.t_lo[src];
+    s.u[k] = s.t_u[src];
+    s.q[k] = s.t_q[src];
+    s.drho[k] = s.t_drho[src];
+    s.acc[k] = s.t_acc[src];
+    s.id[k] = s.t_id[src];
+    s.cell[k] = s.t_key[src];
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+    s.count[c0 + i] = 0;
+    s.cursor[c0 + i] = 0;
+  }
+}
+
+// Start of a step: clear the rebin request (after the gated kernels read it)
+// and the next step's max-speed accumulators.
+__global__ void k_step_begin(unsigned* flags, unsigned* umax_nxt, int R) {
+  const int t = threadIdx.x;
+  if (t == 0) flags[1] = 0u;
+  for (int r = t; r < R; r += blockDim.x) umax_nxt[r] = 0u;
+}
+
+// Sorted state of replica r -> FP64 arrays in id order at the integer time
+// level: r^n = r^{n+1/2} - u^{n+1/2} dt/2, u^n = u^{n+1/2} - a dt/2.
+__global__ void k_export(SortArgs s, int r, double* out, int n) {
+  const RepDev R = s.reps[r];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma clang fp contract(off)
+    const int k = R.part_base + i;
+    const int id = s.id[k];
+    if (id < 0 || id >= n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const int c = s.cell[k] - R.cell_base;
+    const int cx = c % R.nc, cy = c / R.nc;
+    const float2 o = s.off[k], lo = s.offlo[k], uh = s.u[k], ac = s.acc[k], q = s.q[k];
+    const double hdt = 0.5 * (double)R.dt;
+    const double uxn = (double)uh.x - hdt * (double)ac.x;
+    const double uyn = (double)uh.y - hdt * (double)ac.y;
+    double x = (double)cx * R.csd + ((double)o.x + (double)lo.x) - hdt * (double)uh.x;
+    double y = (double)cy * R.csd + ((double)o.y + (double)lo.y) - hdt * (double)uh.y;
+    x = x - R.Ld * floor(x / R.Ld); if (x >= R.Ld) x -= R.Ld;
+    y = y - R.Ld * floor(y / R.Ld); if (y >= R.Ld) y -= R.Ld;
+    out[id] = x;
+    out[(size_t)n + id] = y;
+    out[2 * (size_t)n + id] = uxn;
+    out[3 * (size_t)n + id] = uyn;
+    out[4 * (size_t)n + id] = (double)q.x;
+    out[5 * (size_t)n + id] = (double)q.y;
+    out[6 * (size_t)n + id] = (double)R.rho0 + (double)s.drho[k];
+    out[7 * (size_t)n + id] = (double)ac.x;
+    out[8 * (size_t)n + id] = (double)ac.y;
+  }
+}
+
+// FP64 reductions of replica r at the integer time level (fixed grid, fixed
+// tree: the result does not depend on scheduling). Stage 1: one partial per
+// block in red[64 + 8*b + k]; stage 2 sums them in order into red[0..7]:
+// sum ux, sum uy, sum |u|^2 / 2, max |u|, max |Q|_F.
+constexpr int RED_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_reduce1(SortArgs s, int r, int n, double* red) {
+  const RepDev R = s.reps[r];
+  __shared__ double sh[5][256];
+  double a0 = 0, a1 = 0, a2 = 0, m0 = 0, m1 = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = R.part_base + i;
+    const float2 uh = s.u[k], ac = s.acc[k], q = s.q[k];
+    const double hdt = 0.5 * (double)R.dt;
+    const double ux = (double)uh.x - hdt * (double)ac.x, uy = (double)uh.y - hdt * (double)ac.y;
+    const double u2 = ux * ux + uy * uy;
+    a0 += ux; a1 += uy; a2 += 0.5 * u2;
+    m0 = fmax(m0, sqrt(u2));
+    m1 = fmax(m1, sqrt(2.0 * ((double)q.x * q.x + (double)q.y * q.y)));
+  }
+  const int t = threadIdx.x;
+  sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = m0; sh[4][t] = m1;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (t < d) {
+      sh[0][t] += sh[0][t + d]; sh[1][t] += sh[1][t + d]; sh[2][t] += sh[2][t + d];
+      sh[3][t] = fmax(sh[3][t], sh[3][t + d]); sh[4][t] = fmax(sh[4][t], sh[4][t + d]);
+    }
+    __syncthreads();
+  }
+  if (t < 5) red[64 + 8 * blockIdx.x + t] = sh[t][0];
+}
+__global__ void k_reduce2(double* red) {
+  if (threadIdx.x != 0) return;
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int b = 0; b < RED_BLOCKS; ++b) {
+    for (int k = 0; k < 3; ++k) v[k] += red[64 + 8 * b + k];
+    for (int k = 3; k < 5; ++k) v[k] = fmax(v[k], red[64 + 8 * b + k]);
+  }
+  for (int k = 0; k < 5; ++k) red[k] = v[k];
+}
+
+// -------------------------------------------------------------- launchers
+static int grid_for(int n) { return max(1, min((n + 255) / 256, 2048)); }
+
+void launch_ingest(const SortArgs& s, int r, const double* in, int n, unsigned* umax, hipStream_t st) {
+  hipLaunchKernelGGL(k_ingest, dim3(grid_for(n)), dim3(256), 0, st, s, r, in, n, umax);
+}
+void launch_rebin_key(const SortArgs& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_rebin_key, dim3(grid_for(s.ntot)), dim3(256), 0, st, s);
+}
+void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s, c0, nc, base);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, s, k0, n);
+  hipLaunchKernelGGL(k_cellsort, dim3(grid_for(nc)), dim3(256), 0, st, s, c0, nc);
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(max(n, nc))), dim3(256), 0, st, s, k0, n, c0, nc);
+}
+void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, st, flags, umax_nxt, R);
+}
+void launch_reduce(const SortArgs& s, int r, int n, double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, st, s, r, n, red);
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, st, red);
+}
+void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_export, dim3(grid_for(n)), dim3(256), 0, st, s, r, out, n);
+}
+
+}  // namespace nem

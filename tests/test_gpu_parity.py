@@ -1,0 +1,243 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs. Bars: neighbour sets bit-exact; fields within 1e-5
+relative L2 over 10-step horizons (FP32 pair arithmetic with compensated
+sums against FP64)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import field_errors, gpu_run, random_state, run_oracle  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_08919_amd as P
+    P.lib()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# --------------------------------------------------------------- neighbours
+
+def csr_rows(rp, col):
+    return [tuple(col[rp[i]:rp[i + 1]].tolist()) for i in range(rp.size - 1)]
+
+
+@pytest.mark.parametrize("kind,L,seed", [("lattice", 16, 0), ("lattice", 64, 0), ("jitter", 24, 1),
+                                         ("uniform", 16, 2), ("uniform", 24, 3), ("uniform", 40, 4)])
+def test_neighbors_bit_exact(kind, L, seed):
+    import paper_2108_08919_amd as P
+    p = wl.Params(L=float(L))
+    if kind == "lattice":
+        x, y = wl.lattice(L)
+    elif kind == "jitter":
+        x, y = wl.jittered_lattice(L, 1.0, 0.4, seed)
+    else:
+        x, y = wl.uniform_positions(L * L, float(L), seed)
+    n = x.size
+    z = np.zeros(n)
+    s0 = dict(x=x, y=y, ux=z, uy=z, qxx=np.ones(n), qxy=z, rho=np.ones(n), ax=z, ay=z)
+    say("neighbors", kind, L, seed, n)
+    sim = P.Sim([p], [n])
+    sim.set_state(0, s0)
+    rp, col = sim.neighbors(0)
+    sim.check()
+    nc = int(np.floor(L / (3 * p.h + p.skin)))
+    orp, ocol = oracle.neighbors(p, x, y, 2, nc)
+    assert csr_rows(rp, col) == csr_rows(orp, ocol)
+    if kind == "lattice":
+        brp, bcol = oracle.neighbors(p, x, y, 1)
+        assert csr_rows(rp, col) == csr_rows(brp, bcol)
+    sim.close()
+
+
+# --------------------------------------------------------------- state I/O
+
+def test_state_roundtrip():
+    L = 32
+    p = wl.Params(L=float(L))
+    s0 = random_state(L, 5, amp_u=1e-2)
+    s0["ax"] = 1e-3 * np.cos(s0["x"])
+    s0["ay"] = 1e-3 * np.sin(s0["y"])
+    say("roundtrip", L)
+    g, sim = gpu_run(p, s0, 0)
+    d = np.abs((g["x"] - s0["x"] + L / 2) % L - L / 2).max()
+    assert d < 1e-9
+    for k in ("ux", "uy", "qxx", "qxy", "ax", "ay"):
+        assert np.allclose(g[k], s0[k], rtol=2e-7, atol=1e-12), k
+    assert np.abs(g["rho"] - s0["rho"]).max() < 1e-10
+    sim.close()
+
+
+# --------------------------------------------------------------- fields
+
+def check(e, tol=TOL, strict_keys=("u", "Q", "rho", "pos")):
+    say({k: f"{v:.3e}" for k, v in e.items()})
+    for k in strict_keys:
+        assert e[k] <= tol, (k, e[k])
+
+
+def test_c1_ten_steps():
+    cfg = wl.config("C1")
+    p = cfg["params"]
+    s0 = wl.state_for(cfg, 0)
+    say("C1 10 steps")
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    e = field_errors(g, o, s0, p.L)
+    check(e)
+    assert e["disp"] < 1e-4 and e["dQ"] < 1e-4
+    sim.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_state_ten_steps(seed):
+    L = 40
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    s0 = random_state(L, seed, amp_u=2e-3)
+    say("random 10 steps", seed)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    e = field_errors(g, o, s0, L)
+    check(e)
+    assert e["disp"] < 1e-4 and e["dQ"] < 1e-4 and e["drho"] < 1e-3
+    sim.close()
+
+
+@pytest.mark.parametrize("opts", [
+    {"comp": 0}, {"comp": 2}, {"tile": 8}, {"lpp": 2}, {"lpp": 4}, {"tile": 8, "lpp": 4}])
+def test_kernel_variants(opts):
+    import paper_2108_08919_amd as P
+    keymap = {"comp": P.NEM_OPT_COMP, "tile": P.NEM_OPT_TILE, "lpp": P.NEM_OPT_LPP}
+    L = 40
+    p = wl.Params(L=float(L), zeta=0.03)
+    s0 = random_state(L, 3, amp_u=2e-3)
+    say("variant", opts)
+    o, _ = run_oracle(p, s0, 5)
+    g, sim = gpu_run(p, s0, 5, {keymap[k]: v for k, v in opts.items()})
+    check(field_errors(g, o, s0, L))
+    sim.close()
+
+
+@pytest.mark.parametrize("form,elastic", [(1, 0), (0, 1)])
+def test_forms(form, elastic):
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.05, form=form, elastic=elastic, K=0.05)
+    s0 = random_state(L, 4, amp_u=2e-3)
+    say("form", form, "elastic", elastic)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    check(field_errors(g, o, s0, L))
+    if form == 1:
+        m = p.rho0 * p.dx ** 2
+        P0 = m * np.array([s0["ux"].sum(), s0["uy"].sum()])
+        d = sim.diagnostics(0)
+        scale = m * np.hypot(s0["ux"], s0["uy"]).sum()
+        assert abs(d["px"] - P0[0]) <= 1e-6 * scale and abs(d["py"] - P0[1]) <= 1e-6 * scale
+    sim.close()
+
+
+def test_uniform_aligned_nematic_at_rest():
+    cfg = wl.config("C1")
+    p = cfg["params"]
+    s0 = wl.state_for(cfg)
+    s0["qxx"] = np.ones_like(s0["qxx"]); s0["qxy"] = np.zeros_like(s0["qxy"])
+    say("uniform nematic")
+    g, sim = gpu_run(p, s0, 100)
+    assert np.all(g["ux"] == 0) and np.all(g["uy"] == 0)
+    assert np.all(g["x"] == s0["x"]) and np.all(g["y"] == s0["y"])
+    assert np.all(g["rho"] == 1.0) and np.all(g["qxy"] == 0)
+    assert np.ptp(g["qxx"]) == 0
+    assert g["qxx"][0] == pytest.approx(0.967626039103667, rel=2e-6)
+    sim.close()
+
+
+def test_rebinning_translation_and_shear():
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.02)
+    s0 = random_state(L, 6, amp_u=0.5)
+    s0["ux"] = s0["ux"] + 23.0            # crosses a cell every ~170 steps, skin/2 in ~2
+    s0["uy"] = s0["uy"] - 17.0
+    say("rebin")
+    o, _ = run_oracle(p, s0, 12)
+    g, sim = gpu_run(p, s0, 12)
+    e = field_errors(g, o, s0, L)
+    check(e, strict_keys=("u", "Q", "rho", "pos"))
+    rp, col = sim.neighbors(0)
+    sim.check()
+    sim.close()
+
+
+def test_deterministic():
+    cfg = wl.config("C1")
+    s0 = random_state(64, 9, amp_u=1e-3)
+    p = cfg["params"]
+    g1, s1 = gpu_run(p, s0, 10)
+    g2, s2 = gpu_run(p, s0, 10)
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k]), k
+    s1.close(); s2.close()
+
+
+def test_resume_from_state():
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.03)
+    s0 = random_state(L, 2, amp_u=2e-3)
+    g10, sa = gpu_run(p, s0, 10)
+    g5, sb = gpu_run(p, s0, 5)
+    g55, sc = gpu_run(p, g5, 5)
+    e = field_errors(g55, g10, s0, L)
+    say(e)
+    assert e["u"] < 1e-6 and e["Q"] < 1e-7 and e["pos_abs_max"] < 1e-9
+    for s in (sa, sb, sc):
+        s.close()
+
+
+def test_nan_reported():
+    import paper_2108_08919_amd as P
+    L = 16
+    p = wl.Params(L=float(L))
+    s0 = random_state(L, 1)
+    s0["qxx"] = s0["qxx"].copy()
+    s0["qxx"][7] = np.nan
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    sim.step(2)
+    assert sim.sync() == P.NEM_E_NUMERIC
+    sim.close()
+
+
+def test_replicas_match_solo_runs():
+    # two boxes of different size and physics advanced in one launch
+    import paper_2108_08919_amd as P
+    pa = wl.Params(L=24.0, zeta=0.03)
+    pb = wl.Params(L=40.0, zeta=0.01, K=0.05)
+    sa, sb = random_state(24, 1), random_state(40, 2)
+    sim = P.Sim([pa, pb], [24 * 24, 40 * 40])
+    sim.set_state(0, sa)
+    sim.set_state(1, sb)
+    sim.step(6)
+    sim.check()
+    ga, gb = sim.get_state(0), sim.get_state(1)
+    ha, x1 = gpu_run(pa, sa, 6)
+    hb, x2 = gpu_run(pb, sb, 6)
+    for k in ga:
+        assert np.array_equal(ga[k], ha[k]), k
+        assert np.array_equal(gb[k], hb[k]), k
+    sim.close(); x1.close(); x2.close()
