@@ -117,8 +117,12 @@ int nem_sync(nem_sim* s);
 
 /* Neighbour lists of replica r at the configuration the next step searches
  * (r^{n+1/2}), in CSR by particle id with ascending columns. The GPU keeps no
- * list: this enumerates pairs with the kernels' own predicate (FP32 cell-
- * relative offsets, 0 < r^2 < fl32((3h)^2), see DESIGN notes in the source).
+ * list: this enumerates pairs with the kernels' own predicate. Positions are
+ * FP32 offsets o from the corner of the particle's cell (cells of side
+ * cs = fl32(L/nc), nc = floor(L/(3h + skin))); for j in the cell displaced by
+ * d in {-1,0,1}^2 from i's cell, r = fl(fl(o_i - o_j) + fl32(-d cs)) per
+ * component, r2 = fl(fl(rx*rx) + fl(ry*ry)) without fused multiply-add, and j
+ * is a neighbour when 0 < r2 < fl32((3h)^2) (Eq. quintic: support 3h).
  * row_ptr has n[r]+1 entries; col has cap entries; *nnz receives the count.
  * Returns NEM_E_NOMEM (with *nnz set) when cap is too small. */
 int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
@@ -127,19 +131,26 @@ int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t
 int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out);
 
 /* Tuning and instrumentation options (key, value):
- *   NEM_OPT_TILE       cells per tile side (2..8)
+ *   NEM_OPT_TILE       cells per tile side (4 or 8)
  *   NEM_OPT_LPP        lanes per particle in the pair loops (1, 2 or 4)
  *   NEM_OPT_COMP       pair-sum compensation: 0 none, 1 per stencil cell, 2 per pair
- *   NEM_OPT_TIMING     1: record HIP events around every pass launch */
+ *   NEM_OPT_TIMING     1: record HIP events around every pass launch
+ *   NEM_OPT_GRAPH      1: capture one step per buffer parity into a hipGraph
+ *                      and replay it (ignored while timing is on)
+ * Changing an option drops captured graphs. */
 #define NEM_OPT_TILE 1
 #define NEM_OPT_LPP 2
 #define NEM_OPT_COMP 3
 #define NEM_OPT_TIMING 4
+#define NEM_OPT_GRAPH 5
 int nem_set_option(nem_sim* s, int32_t key, int64_t value);
 
-/* Accumulated kernel times (ms) and launch counts since the last reset, per
- * pass: 0 rebin, 1 pass A (volume), 2 pass B (gradients and rates), 3 pass C
- * (filter and EoS), 4 pass D (stress and update). Requires NEM_OPT_TIMING. */
+/* Accumulated kernel times (ms, from HIP events recorded on the library's
+ * stream around each launch group) and launch counts since the last reset,
+ * per pass: 0 rebin (five kernels that return at once unless a rebin was
+ * requested), 1 pass A (volume), 2 pass B (gradients and rates), 3 pass C
+ * (filter and EoS), 4 pass D (stress and update). Requires NEM_OPT_TIMING;
+ * synchronises the stream. */
 #define NEM_NPASS 5
 int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset);
 

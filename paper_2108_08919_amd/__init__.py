@@ -33,6 +33,7 @@ NEM_OPT_TILE = 1
 NEM_OPT_LPP = 2
 NEM_OPT_COMP = 3
 NEM_OPT_TIMING = 4
+NEM_OPT_GRAPH = 5
 NEM_NPASS = 5
 PASS_NAMES = ("rebin", "pass_a_volume", "pass_b_rates", "pass_c_eos", "pass_d_update")
 

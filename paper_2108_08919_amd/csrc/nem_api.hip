@@ -48,7 +48,12 @@ struct nem_sim {
   std::vector<char> has_state;
   int T = 4, LPP = 1, COMP = 1;
   int timing = 0;
-  std::vector<hipEvent_t> evs;
+  struct EvRec { int pass; hipEvent_t a, b; };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<EvRec> ev_pend;
+  int use_graph = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   double pass_ms[NEM_NPASS] = {0};
   int64_t pass_n[NEM_NPASS] = {0};
   std::string err;
@@ -249,27 +254,94 @@ int status_from_flags(nem_sim* s, unsigned f) {
   return NEM_OK;
 }
 
+hipEvent_t take_event(nem_sim* s) {
+  if (!s->ev_free.empty()) { hipEvent_t e = s->ev_free.back(); s->ev_free.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Accumulate the durations of all recorded launches (synchronises the stream).
+void collect_times(nem_sim* s) {
+  if (s->ev_pend.empty()) return;
+  hipStreamSynchronize(s->stream);
+  for (auto& r : s->ev_pend) {
+    float ms = 0.f;
+    if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      s->pass_ms[r.pass] += ms;
+      s->pass_n[r.pass] += 1;
+    }
+    if (r.a) s->ev_free.push_back(r.a);
+    if (r.b) s->ev_free.push_back(r.b);
+  }
+  s->ev_pend.clear();
+}
+
+// HIP events around one launch group on the library's stream (timing mode).
 struct Timed {
   nem_sim* s;
-  int pass;
-  Timed(nem_sim* s_, int p) : s(s_), pass(p) {
-    if (s->timing) hipEventRecord(s->evs[2 * pass], s->stream);
+  nem_sim::EvRec rec{0, nullptr, nullptr};
+  Timed(nem_sim* s_, int p) : s(s_) {
+    if (!s->timing) return;
+    rec.pass = p;
+    rec.a = take_event(s);
+    if (rec.a) hipEventRecord(rec.a, s->stream);
   }
   ~Timed() {
-    if (s->timing) hipEventRecord(s->evs[2 * pass + 1], s->stream);
+    if (!s->timing) return;
+    rec.b = take_event(s);
+    if (rec.b) hipEventRecord(rec.b, s->stream);
+    s->ev_pend.push_back(rec);
+    if (s->ev_pend.size() > 8192) collect_times(s);
   }
 };
 
-void collect_times(nem_sim* s) {
-  if (!s->timing) return;
-  hipStreamSynchronize(s->stream);
-  for (int p = 0; p < NEM_NPASS; ++p) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->evs[2 * p], s->evs[2 * p + 1]) == hipSuccess) {
-      s->pass_ms[p] += ms;
-      s->pass_n[p] += 1;
-    }
+// Enqueue one step (rebin if requested, step-begin, passes A-D) on stream st
+// for the current parity.
+int enqueue_step(nem_sim* s, hipStream_t st) {
+  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic};
+  {
+    Timed t(s, 0);
+    SortArgs a = sort_args(s, s->flags + 1);
+    launch_rebin_key(a, st);
+    launch_sort_tail(a, 0, s->ntot, 0, s->ncells, 0, st);
   }
+  StepArgs a = step_args(s);
+  launch_step_begin(s->flags, a.umax_nxt, s->R, st);
+  for (int pass = 1; pass <= 4; ++pass) {
+    Timed t(s, pass);
+    if (!launch_pass(pass, cfg, a, st)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
+  }
+  HIPCHK(hipGetLastError());
+  return NEM_OK;
+}
+
+void drop_graphs(nem_sim* s) {
+  for (auto& g : s->graph)
+    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+}
+
+// Capture the step of each parity into a graph (once per configuration).
+int capture_graphs(nem_sim* s) {
+  if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  const int saved = s->parity;
+  for (int par = 0; par < 2; ++par) {
+    s->parity = par;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int timing = s->timing;
+    s->timing = 0;
+    int rc = enqueue_step(s, s->cap_stream);
+    s->timing = timing;
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (rc) { if (g) hipGraphDestroy(g); s->parity = saved; return rc; }
+    if (e != hipSuccess) { s->parity = saved; return hip_fail(s, e, "hipStreamEndCapture"); }
+    e = hipGraphInstantiate(&s->graph[par], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) { s->parity = saved; return hip_fail(s, e, "hipGraphInstantiate"); }
+  }
+  s->parity = saved;
+  return NEM_OK;
 }
 
 }  // namespace
@@ -418,22 +490,18 @@ int nem_step(nem_sim* s, int64_t nsteps) {
   if (!s || nsteps < 0) return NEM_E_INVAL;
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) { s->err = "nem_set_state was not called for every replica"; return NEM_E_STATE; }
-  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic};
+  const bool graph = s->use_graph && !s->timing;
+  if (graph && !s->graph[0]) {
+    int rc = capture_graphs(s);
+    if (rc) { drop_graphs(s); return rc; }
+  }
   for (int64_t it = 0; it < nsteps; ++it) {
-    {
-      Timed t(s, 0);
-      SortArgs a = sort_args(s, s->flags + 1);
-      launch_rebin_key(a, s->stream);
-      launch_sort_tail(a, 0, s->ntot, 0, s->ncells, 0, s->stream);
+    if (graph) {
+      HIPCHK(hipGraphLaunch(s->graph[s->parity], s->stream));
+    } else {
+      int rc = enqueue_step(s, s->stream);
+      if (rc) return rc;
     }
-    StepArgs a = step_args(s);
-    launch_step_begin(s->flags, const_cast<unsigned*>(a.umax_nxt), s->R, s->stream);
-    for (int pass = 1; pass <= 4; ++pass) {
-      Timed t(s, pass);
-      if (!launch_pass(pass, cfg, a, s->stream)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
-    }
-    HIPCHK(hipGetLastError());
-    collect_times(s);
     s->parity ^= 1;
   }
   return NEM_OK;
@@ -442,6 +510,7 @@ int nem_step(nem_sim* s, int64_t nsteps) {
 int nem_sync(nem_sim* s) {
   if (!s) return NEM_E_INVAL;
   HIPCHK(hipStreamSynchronize(s->stream));
+  collect_times(s);
   unsigned f[2];
   int rc = read_flags(s, f);
   if (rc) return rc;
@@ -519,23 +588,27 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
   switch (key) {
     case NEM_OPT_TILE: {
       if (value != 4 && value != 8) return NEM_E_INVAL;
+      drop_graphs(s);
       s->T = (int)value;
       return build_work(s);
     }
     case NEM_OPT_LPP:
       if (value != 1 && value != 2 && value != 4) return NEM_E_INVAL;
+      drop_graphs(s);
       s->LPP = (int)value;
       return NEM_OK;
     case NEM_OPT_COMP:
       if (value < 0 || value > 2) return NEM_E_INVAL;
+      drop_graphs(s);
       s->COMP = (int)value;
       return NEM_OK;
     case NEM_OPT_TIMING:
-      if (value && s->evs.empty()) {
-        s->evs.resize(2 * NEM_NPASS);
-        for (auto& e : s->evs) HIPCHK(hipEventCreate(&e));
-      }
+      collect_times(s);
       s->timing = value ? 1 : 0;
+      return NEM_OK;
+    case NEM_OPT_GRAPH:
+      drop_graphs(s);
+      s->use_graph = value ? 1 : 0;
       return NEM_OK;
     default:
       return NEM_E_INVAL;
@@ -544,6 +617,7 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
 
 int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset) {
   if (!s) return NEM_E_INVAL;
+  collect_times(s);
   for (int p = 0; p < NEM_NPASS; ++p) {
     if (ms) ms[p] = s->pass_ms[p];
     if (launches) launches[p] = s->pass_n[p];
@@ -556,7 +630,10 @@ void nem_destroy(nem_sim* s) {
   if (!s) return;
   if (s->stream) hipStreamSynchronize(s->stream);
   else hipDeviceSynchronize();
-  for (auto& e : s->evs) hipEventDestroy(e);
+  collect_times(s);
+  for (auto& e : s->ev_free) hipEventDestroy(e);
+  drop_graphs(s);
+  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
   if (s->own && s->arena) hipFree(s->arena);
   delete s;
 }

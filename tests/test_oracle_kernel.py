@@ -74,7 +74,7 @@ def test_lattice_volume_and_correction(hdx):
 
 
 def test_lattice_sums_reference_values():
-    # FP64 lattice sums for dx = 1, h = 1.3 (values recorded in the design doc);
+    # FP64 lattice sums for dx = 1, h = 1.3 (regression values of this oracle);
     # they follow from the pins above and fix the digits.
     p = wl.Params(L=16.0, h=1.3)
     x, y = wl.lattice(16)

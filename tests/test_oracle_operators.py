@@ -56,7 +56,7 @@ def test_laplacian_plane_wave_eigen(L, m, ratio_min):
     ratio = lam / (-k * k)
     assert ratio_min < ratio <= 1.0 + 1e-9
     if (L, m) == (64, 1):
-        # value recorded in the design doc: symbol -0.0096193344248 vs exact -(2pi/64)^2
+        # lattice symbol -0.0096193344248 against the exact -(2pi/64)^2
         assert lam == pytest.approx(-0.0096193344248, rel=1e-9)
 
 
