@@ -127,8 +127,33 @@ int nem_sync(nem_sim* s);
  * Returns NEM_E_NOMEM (with *nnz set) when cap is too small. */
 int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
 
-/* FP64 reductions of replica r at the current integer time level. */
+/* FP64 reductions of replica r at the current integer time level: momentum,
+ * kinetic energy, max |u|, max |Q| (from the stored state), and the free energy
+ * of Eq. freeenergy with the elastic part through the discrete Laplacian (F)
+ * and through squared corrected gradients (F_grad), whose pair sums are taken
+ * at r^n (this reuses the per-step work arrays, so call it between steps). */
 int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out);
+
+/* Grid diagnostics of replica r at the integer time level (paper Sec. 5).
+ * All three first Shepard-interpolate u and Q onto an M x M grid (M a power of
+ * two in [8, 2048]; nodes at ((i+1/2) L/M, (j+1/2) L/M)): f_g = sum_j f_j W_gj /
+ * sum_j W_gj over particles within 3h. These calls allocate grid buffers on the
+ * device on first use (freed by nem_destroy) and synchronise the stream.
+ *
+ * nem_deposit: copies the grid to out[4*M*M] = (ux, uy, Qxx, Qxy), each row major
+ *   (out[f*M*M + j*M + i]).
+ * nem_spectrum: kinetic-energy spectrum E(n) = 1/2 sum_{shell n} |u^(k)|^2 / M^4
+ *   with shell n = floor(|k| L/2pi + 1/2) (so sum_n E(n) = <|u|^2>/2 over the grid),
+ *   from a double-precision 2D FFT; E has nbins entries (shells beyond
+ *   floor(sqrt(2) M/2 + 1/2) are zero); *slope (may be NULL) is the least-squares
+ *   slope of ln E on ln n over k_lo..k_hi (<= 0 selects 4 and M/8).
+ * nem_defects: counts of +1/2 and -1/2 defects: director angle atan2(Qxy,Qxx)/2
+ *   per node, winding around each unit plaquette with edge differences wrapped
+ *   into (-pi/2, pi/2]; a total of +pi (-pi) is a +1/2 (-1/2) defect. */
+int nem_deposit(nem_sim* s, int32_t r, int32_t M, double* out);
+int nem_spectrum(nem_sim* s, int32_t r, int32_t M, double* E, int32_t nbins, int32_t k_lo, int32_t k_hi,
+                 double* slope);
+int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus);
 
 /* Tuning and instrumentation options (key, value):
  *   NEM_OPT_TILE       cells per tile side (4 or 8)
@@ -153,6 +178,54 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value);
  * synchronises the stream. */
 #define NEM_NPASS 5
 int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset);
+
+/* ---------------------------------------------------------------------------
+ * Learned corrector: macro steps of mult*dt whose Q and u are corrected by a
+ * 12 -> 64 -> 64 -> 5 perceptron (tanh, linear output) on BF16 matrix cores
+ * with FP32 accumulation, trained on samples the solver generates, with mult
+ * plain steps of dt as the fallback.
+ *
+ * Inputs per particle (12): Qxx, Qxy, Qyy, du_x/dx, du_x/dy, du_y/dx, du_y/dy,
+ * Hxx, Hxy, Hyy, (rho - rho0)/rho0, zeta, taken in pass B of the macro step;
+ * outputs (5): corrections of Qxx, Qxy, Qyy, u_x, u_y (Q projected traceless).
+ * Inputs and targets are z-scored with stored means and standard deviations.
+ * Weights: flat FP32 vector W1 (12x64, input-major), b1, W2 (64x64), b2,
+ * W3 (64x5), b3 (nem_mlp_nparams() values). Device pointers (X, T, Y) are
+ * caller-owned device memory; they must stay valid during the call.
+ * ------------------------------------------------------------------------- */
+typedef struct nem_mlp nem_mlp;
+int nem_mlp_nparams(void);
+/* Network with zero weights and identity normalisation on hip_stream. */
+int nem_mlp_create(void* hip_stream, nem_mlp** out);
+int nem_mlp_set_weights(nem_mlp* m, const float* w);   /* host, resets Adam */
+int nem_mlp_get_weights(nem_mlp* m, float* w);         /* host */
+/* norm[34]: input means (12), input std (12), target means (5), target std (5). */
+int nem_mlp_set_norm(nem_mlp* m, const float* norm);
+int nem_mlp_get_norm(nem_mlp* m, float* norm);
+/* Normalisation fitted (FP64 on the device) to X (n x 12) and T (n x 5). */
+int nem_mlp_fit_norm(nem_mlp* m, const float* X, const float* T, int64_t n);
+/* Y (n x 5, physical units) = network(X (n x 12)). */
+int nem_mlp_forward(nem_mlp* m, const float* X, int64_t n, float* Y);
+/* Gradient (host, nem_mlp_nparams() values) of L = (1/2n) sum |y - t|^2 in
+ * normalised units over all n samples; *loss may be NULL. */
+int nem_mlp_grad(nem_mlp* m, const float* X, const float* T, int64_t n, float* grad, double* loss);
+/* Adam (0.9, 0.999, 1e-8) over `epochs` passes of minibatches of `batch`
+ * samples (a deterministic per-epoch permutation); *final_loss = last batch. */
+int nem_mlp_train(nem_mlp* m, const float* X, const float* T, int64_t n, int32_t epochs, int32_t batch,
+                  double lr, double* final_loss);
+void nem_mlp_destroy(nem_mlp* m);
+
+/* Training samples at the current state of every replica, particle
+ * (part_base(r) + id): X (ntot x 12) inputs of a step of mult*dt, T (ntot x 5)
+ * = (Q, u after mult steps of dt) - (Q, u after one step of mult*dt). The
+ * state is left unchanged. Allocates a scratch buffer (hipMalloc). */
+int nem_samples(nem_sim* s, int32_t mult, float* X, float* T);
+/* n_macro macro steps of mult*dt with corrections; a macro step whose largest
+ * correction norm (normalised units) exceeds tau is replayed as mult steps of
+ * dt. Synchronises once per macro step (one word read back); allocates
+ * scratch buffers (hipMalloc). *n_fallback and *max_norm may be NULL. */
+int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, double tau, int64_t* n_fallback,
+                     double* max_norm);
 
 /* Error text for a status code, and the last error recorded on a solver. */
 const char* nem_strerror(int code);

@@ -38,8 +38,11 @@ NEM_NPASS = 5
 PASS_NAMES = ("rebin", "pass_a_volume", "pass_b_rates", "pass_c_eos", "pass_d_update")
 
 EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "nem_get_state", "nem_step",
-            "nem_sync", "nem_neighbors", "nem_diagnostics", "nem_set_option", "nem_pass_times",
-            "nem_strerror", "nem_last_error", "nem_destroy")
+            "nem_sync", "nem_neighbors", "nem_diagnostics", "nem_deposit", "nem_spectrum", "nem_defects",
+            "nem_set_option", "nem_pass_times", "nem_strerror", "nem_last_error", "nem_destroy",
+            "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
+            "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
+            "nem_mlp_destroy", "nem_samples", "nem_step_learned")
 
 
 class NemParams(C.Structure):
@@ -95,10 +98,37 @@ def lib(path: Optional[str] = None):
                                 C.POINTER(C.c_int64)]
     L.nem_diagnostics.restype = C.c_int
     L.nem_diagnostics.argtypes = [vp, C.c_int32, C.POINTER(NemDiag)]
+    L.nem_deposit.restype = C.c_int
+    L.nem_deposit.argtypes = [vp, C.c_int32, C.c_int32, dp]
+    L.nem_spectrum.restype = C.c_int
+    L.nem_spectrum.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, C.c_int32, dp]
+    L.nem_defects.restype = C.c_int
+    L.nem_defects.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.nem_set_option.restype = C.c_int
     L.nem_set_option.argtypes = [vp, C.c_int32, C.c_int64]
     L.nem_pass_times.restype = C.c_int
     L.nem_pass_times.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
+    fp = C.POINTER(C.c_float)
+    L.nem_mlp_nparams.restype = C.c_int
+    L.nem_mlp_create.restype = C.c_int
+    L.nem_mlp_create.argtypes = [vp, C.POINTER(vp)]
+    for name in ("nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm", "nem_mlp_get_norm"):
+        getattr(L, name).restype = C.c_int
+        getattr(L, name).argtypes = [vp, fp]
+    L.nem_mlp_fit_norm.restype = C.c_int
+    L.nem_mlp_fit_norm.argtypes = [vp, vp, vp, C.c_int64]
+    L.nem_mlp_forward.restype = C.c_int
+    L.nem_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+    L.nem_mlp_grad.restype = C.c_int
+    L.nem_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, fp, dp]
+    L.nem_mlp_train.restype = C.c_int
+    L.nem_mlp_train.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_double, dp]
+    L.nem_mlp_destroy.restype = None
+    L.nem_mlp_destroy.argtypes = [vp]
+    L.nem_samples.restype = C.c_int
+    L.nem_samples.argtypes = [vp, C.c_int32, vp, vp]
+    L.nem_step_learned.restype = C.c_int
+    L.nem_step_learned.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_double, C.POINTER(C.c_int64), dp]
     L.nem_strerror.restype = C.c_char_p
     L.nem_strerror.argtypes = [C.c_int]
     L.nem_last_error.restype = C.c_char_p
@@ -207,6 +237,26 @@ def nem_diagnostics(h, r) -> Dict[str, float]:
     return {k: getattr(d, k) for k, _ in NemDiag._fields_}
 
 
+def nem_deposit(h, r, M):
+    out = np.zeros((4, M, M))
+    _check(h, lib().nem_deposit(C.c_void_p(h), r, M, _dp(out)), "nem_deposit")
+    return out
+
+
+def nem_spectrum(h, r, M, k_lo: int = 0, k_hi: int = 0):
+    nb = int(np.floor(np.sqrt(2.0) * (M // 2) + 0.5)) + 1
+    E = np.zeros(nb)
+    sl = C.c_double(0.0)
+    _check(h, lib().nem_spectrum(C.c_void_p(h), r, M, _dp(E), nb, k_lo, k_hi, C.byref(sl)), "nem_spectrum")
+    return E, sl.value
+
+
+def nem_defects(h, r, M):
+    a, b = C.c_int64(0), C.c_int64(0)
+    _check(h, lib().nem_defects(C.c_void_p(h), r, M, C.byref(a), C.byref(b)), "nem_defects")
+    return a.value, b.value
+
+
 def nem_set_option(h, key: int, value: int):
     _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
 
@@ -222,6 +272,87 @@ def nem_pass_times(h, reset: bool = False):
 def nem_destroy(h):
     if h:
         lib().nem_destroy(C.c_void_p(h))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _mcheck(rc, what):
+    if rc:
+        raise NemError(rc, what)
+
+
+class Mlp:
+    """The learned corrector's network (BF16 MFMA kernels, FP32 master weights).
+    Device arrays are torch float32 tensors on the GPU."""
+
+    NI, NO = 12, 5
+
+    def __init__(self, stream=None):
+        import torch
+        lib()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = st
+        h = C.c_void_p(0)
+        _mcheck(lib().nem_mlp_create(C.c_void_p(st.cuda_stream or None), C.byref(h)), "nem_mlp_create")
+        self.h = h.value
+        self.nparams = lib().nem_mlp_nparams()
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.nparams
+        _mcheck(lib().nem_mlp_set_weights(C.c_void_p(self.h), _fp(w)), "nem_mlp_set_weights")
+
+    def get_weights(self):
+        w = np.zeros(self.nparams, dtype=np.float32)
+        _mcheck(lib().nem_mlp_get_weights(C.c_void_p(self.h), _fp(w)), "nem_mlp_get_weights")
+        return w
+
+    def set_norm(self, norm):
+        nm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert nm.size == 34
+        _mcheck(lib().nem_mlp_set_norm(C.c_void_p(self.h), _fp(nm)), "nem_mlp_set_norm")
+
+    def get_norm(self):
+        nm = np.zeros(34, dtype=np.float32)
+        _mcheck(lib().nem_mlp_get_norm(C.c_void_p(self.h), _fp(nm)), "nem_mlp_get_norm")
+        return nm
+
+    def fit_norm(self, X, T):
+        _mcheck(lib().nem_mlp_fit_norm(C.c_void_p(self.h), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                       X.shape[0]), "nem_mlp_fit_norm")
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.NO), dtype=torch.float32, device=X.device)
+        _mcheck(lib().nem_mlp_forward(C.c_void_p(self.h), C.c_void_p(X.data_ptr()), X.shape[0],
+                                      C.c_void_p(Y.data_ptr())), "nem_mlp_forward")
+        return Y
+
+    def grad(self, X, T):
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = C.c_double(0)
+        _mcheck(lib().nem_mlp_grad(C.c_void_p(self.h), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                   X.shape[0], _fp(g), C.byref(loss)), "nem_mlp_grad")
+        return g, loss.value
+
+    def train(self, X, T, epochs: int, batch: int, lr: float) -> float:
+        loss = C.c_double(0)
+        _mcheck(lib().nem_mlp_train(C.c_void_p(self.h), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                    X.shape[0], epochs, batch, lr, C.byref(loss)), "nem_mlp_train")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nem_mlp_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- wrapper
@@ -266,6 +397,32 @@ class Sim:
 
     def diagnostics(self, r: int = 0):
         return nem_diagnostics(self.h, r)
+
+    def deposit(self, r: int = 0, M: int = 0):
+        return nem_deposit(self.h, r, M or int(self.params[r].L))
+
+    def spectrum(self, r: int = 0, M: int = 0, k_lo: int = 0, k_hi: int = 0):
+        return nem_spectrum(self.h, r, M or int(self.params[r].L), k_lo, k_hi)
+
+    def defects(self, r: int = 0, M: int = 0):
+        return nem_defects(self.h, r, M or int(self.params[r].L))
+
+    def samples(self, mult: int = 4):
+        """Training inputs X (ntot x 12) and targets T (ntot x 5) at the current state."""
+        import torch
+        N = sum(self.n)
+        X = torch.empty((N, 12), dtype=torch.float32, device=self.device)
+        T = torch.empty((N, 5), dtype=torch.float32, device=self.device)
+        _check(self.h, lib().nem_samples(C.c_void_p(self.h), mult, C.c_void_p(X.data_ptr()),
+                                         C.c_void_p(T.data_ptr())), "nem_samples")
+        return X, T
+
+    def step_learned(self, mlp: "Mlp", n_macro: int, mult: int = 4, tau: float = 1e30):
+        nfb = C.c_int64(0)
+        mx = C.c_double(0)
+        _check(self.h, lib().nem_step_learned(C.c_void_p(self.h), C.c_void_p(mlp.h), n_macro, mult, tau,
+                                              C.byref(nfb), C.byref(mx)), "nem_step_learned")
+        return nfb.value, mx.value
 
     def set_option(self, key: int, value: int):
         nem_set_option(self.h, key, value)

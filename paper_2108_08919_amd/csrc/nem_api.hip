@@ -16,50 +16,14 @@
 
 #include "../../include/nematic_sph.h"
 #include "nem_dev.h"
+#include "nem_sim.h"
 
 
 using namespace nem;
+using namespace nem_host;
 
-struct nem_sim {
-  int R = 0;
-  std::vector<nem_params> hp;
-  std::vector<int64_t> n;
-  int ntot = 0, ncells = 0;
-  std::vector<RepDev> reps;
-  hipStream_t stream = nullptr;
-  char* arena = nullptr;
-  size_t arena_bytes = 0;
-  bool own = false;
-  RepDev* d_reps = nullptr;
-  int* d_work = nullptr;
-  int nwork = 0, work_cap = 0;
-  int *cell_start = nullptr, *count = nullptr, *cursor = nullptr, *perm = nullptr;
-  int* t_key = nullptr; float2 *t_off = nullptr, *t_lo = nullptr, *t_u = nullptr, *t_q = nullptr;
-  float* t_drho = nullptr; float2* t_acc = nullptr; int* t_id = nullptr;
-  float2* off[2] = {nullptr, nullptr}; float2* offlo = nullptr; float2* u = nullptr;
-  float2* q[2] = {nullptr, nullptr}; float* drho = nullptr; float2* acc = nullptr;
-  int* id = nullptr; int* cell = nullptr;
-  float* V = nullptr; float4* bk = nullptr; float* dh = nullptr; float2* apart = nullptr;
-  float* uv = nullptr; float2* pi = nullptr; float* P = nullptr; float* drhat = nullptr;
-  unsigned* flags = nullptr; unsigned* umax = nullptr;
-  double* stage = nullptr; int64_t stage_n = 0;
-  double* red = nullptr;
-  int parity = 0;
-  std::vector<char> has_state;
-  int T = 4, LPP = 1, COMP = 1;
-  int timing = 0;
-  struct EvRec { int pass; hipEvent_t a, b; };
-  std::vector<hipEvent_t> ev_free;
-  std::vector<EvRec> ev_pend;
-  int use_graph = 0;
-  hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  double pass_ms[NEM_NPASS] = {0};
-  int64_t pass_n[NEM_NPASS] = {0};
-  std::string err;
-};
 
-namespace {
+namespace nem_host {
 
 constexpr size_t ALIGN = 256;
 
@@ -117,7 +81,7 @@ struct Offs {
   size_t reps, work, cell_start, count, cursor, perm;
   size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id;
   size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell;
-  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red;
+  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe;
   size_t total;
 };
 
@@ -158,7 +122,11 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.P = L.put(sizeof(float) * N);
   o.drhat = L.put(sizeof(float) * N);
   o.flags = L.put(sizeof(unsigned) * 4);
-  o.umax = L.put(sizeof(unsigned) * 2 * R);
+  o.umax = L.put(sizeof(unsigned) * 2 * R * UMAX_SLOTS);
+  o.nl = L.put(sizeof(uint32_t) * (KMAX / 2) * N);
+  o.ncnt = L.put(sizeof(int) * N);
+  o.apdg = L.put(sizeof(float4) * N);
+  o.fe = L.put(sizeof(double) * 2 * N);
   o.stage = L.put(sizeof(double) * 9 * (size_t)stage_n);
   o.red = L.put(sizeof(double) * 64 * 1024);
   o.total = L.total + ALIGN;
@@ -186,16 +154,6 @@ int sizes_for(const nem_params* p, const int64_t* n, int R, Sizes& s, std::strin
   return NEM_OK;
 }
 
-int hip_fail(nem_sim* s, hipError_t e, const char* what) {
-  if (s) s->err = std::string(what) + ": " + hipGetErrorString(e);
-  return NEM_E_HIP;
-}
-#define HIPCHK(expr)                                        \
-  do {                                                      \
-    hipError_t e_ = (expr);                                 \
-    if (e_ != hipSuccess) return hip_fail(s, e_, #expr);   \
-  } while (0)
-
 SortArgs sort_args(nem_sim* s, const unsigned* gate) {
   SortArgs a;
   a.reps = s->d_reps; a.R = s->R; a.ncells = s->ncells; a.ntot = s->ntot;
@@ -211,13 +169,15 @@ SortArgs sort_args(nem_sim* s, const unsigned* gate) {
 StepArgs step_args(nem_sim* s) {
   StepArgs a;
   const int c = s->parity, x = 1 - s->parity;
-  a.reps = s->d_reps; a.work = s->d_work; a.nwork = s->nwork; a.T = s->T;
+  a.reps = s->d_reps; a.work = s->d_work; a.nwork = s->nwork; a.T = s->T; a.lpp = s->LPP;
   a.cell_start = s->cell_start; a.ncells = s->ncells; a.ntot = s->ntot;
   a.off_cur = s->off[c]; a.off_nxt = s->off[x]; a.offlo = s->offlo; a.u = s->u;
   a.q_cur = s->q[c]; a.q_nxt = s->q[x]; a.acc = s->acc; a.drho = s->drho; a.cell = s->cell;
   a.V = s->V; a.bk = s->bk; a.dh = s->dh; a.apart = s->apart; a.uv = s->uv; a.pi = s->pi;
   a.P = s->P; a.drhat = s->drhat; a.flags = s->flags;
-  a.umax_cur = s->umax + (size_t)c * s->R; a.umax_nxt = s->umax + (size_t)x * s->R;
+  a.umax_cur = s->umax + (size_t)c * s->R * UMAX_SLOTS; a.umax_nxt = s->umax + (size_t)x * s->R * UMAX_SLOTS;
+  a.nl = s->nl; a.ncnt = s->ncnt; a.apdg = s->apdg;
+  a.feat = s->feat; a.id = s->id;
   return a;
 }
 
@@ -344,7 +304,70 @@ int capture_graphs(nem_sim* s) {
   return NEM_OK;
 }
 
-}  // namespace
+void free_grid(nem_sim* s) {
+  for (void* p : {(void*)s->g_grid, (void*)s->g_z, (void*)s->g_w, (void*)s->g_part, (void*)s->g_E, (void*)s->g_cnt})
+    if (p) hipFree(p);
+  s->g_grid = nullptr; s->g_z = nullptr; s->g_w = nullptr; s->g_part = nullptr; s->g_E = nullptr;
+  s->g_cnt = nullptr; s->gM = 0; s->gbins = 0;
+}
+
+int shell_count(int M) { return (int)std::floor(std::sqrt(2.0) * (M / 2) + 0.5) + 1; }
+
+int ensure_grid(nem_sim* s, int M) {
+  if (s->gM == M) return NEM_OK;
+  free_grid(s);
+  const size_t MM = (size_t)M * M;
+  const int nb = shell_count(M);
+  HIPCHK(hipMalloc((void**)&s->g_grid, sizeof(double) * 4 * MM));
+  HIPCHK(hipMalloc((void**)&s->g_z, sizeof(double2) * MM));
+  HIPCHK(hipMalloc((void**)&s->g_w, sizeof(double2) * MM));
+  HIPCHK(hipMalloc((void**)&s->g_part, sizeof(double) * (size_t)M * nb));
+  HIPCHK(hipMalloc((void**)&s->g_E, sizeof(double) * nb));
+  HIPCHK(hipMalloc((void**)&s->g_cnt, sizeof(unsigned long long) * 2));
+  s->gM = M;
+  s->gbins = nb;
+  return NEM_OK;
+}
+
+// Shepard deposit of replica r onto the M x M grid buffer (device).
+int deposit_grid(nem_sim* s, int r, int M) {
+  if (r < 0 || r >= s->R || M < 8 || M > 2048 || (M & (M - 1))) { s->err = "grid side must be a power of two in [8, 2048]"; return NEM_E_INVAL; }
+  if (!s->has_state[r]) return NEM_E_STATE;
+  int rc = ensure_grid(s, M);
+  if (rc) return rc;
+  SortArgs a = sort_args(s, nullptr);
+  launch_int_offsets(a, s->t_off, s->stream);
+  StepArgs sa = step_args(s);
+  sa.off_cur = s->t_off;
+  launch_deposit(s->T, sa, r, M, s->g_grid, s->stream);
+  HIPCHK(hipGetLastError());
+  return NEM_OK;
+}
+
+int run_steps(nem_sim* s, int64_t nsteps) {
+  const bool graph = s->use_graph && !s->timing && !s->feat;
+  if (graph && !s->graph[0]) {
+    int rc = capture_graphs(s);
+    if (rc) { drop_graphs(s); return rc; }
+  }
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if (graph) {
+      HIPCHK(hipGraphLaunch(s->graph[s->parity], s->stream));
+    } else {
+      int rc = enqueue_step(s, s->stream);
+      if (rc) return rc;
+    }
+    s->parity ^= 1;
+  }
+  return NEM_OK;
+}
+
+int upload_reps(nem_sim* s) {
+  HIPCHK(hipMemcpyAsync(s->d_reps, s->reps.data(), sizeof(RepDev) * s->R, hipMemcpyHostToDevice, s->stream));
+  return NEM_OK;
+}
+
+}  // namespace nem_host
 
 extern "C" {
 
@@ -422,6 +445,8 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   s->P = (float*)(b + o.P); s->drhat = (float*)(b + o.drhat);
   s->flags = (unsigned*)(b + o.flags); s->umax = (unsigned*)(b + o.umax);
   s->stage = (double*)(b + o.stage); s->red = (double*)(b + o.red);
+  s->nl = (uint32_t*)(b + o.nl); s->ncnt = (int*)(b + o.ncnt); s->apdg = (float4*)(b + o.apdg);
+  s->fe = (double*)(b + o.fe);
 
   int cell_base = 0, part_base = 0;
   for (int r = 0; r < R; ++r) {
@@ -454,10 +479,10 @@ int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const
     if (src[f]) HIPCHK(hipMemcpyAsync(dst, src[f], sizeof(double) * n, hipMemcpyHostToDevice, s->stream));
     else HIPCHK(hipMemsetAsync(dst, 0, sizeof(double) * n, s->stream));
   }
-  unsigned* um = s->umax + (size_t)s->parity * s->R + r;
-  HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned), s->stream));
+  unsigned* um = s->umax + ((size_t)s->parity * s->R + r) * UMAX_SLOTS;
+  HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * UMAX_SLOTS, s->stream));
   SortArgs a = sort_args(s, nullptr);
-  launch_ingest(a, r, s->stage, n, s->umax + (size_t)s->parity * s->R, s->stream);
+  launch_ingest(a, r, s->stage, n, s->umax + (size_t)s->parity * s->R * UMAX_SLOTS, s->stream);
   launch_sort_tail(a, R.part_base, n, R.cell_base, R.nc * R.nc, R.part_base, s->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s->stream));
@@ -490,21 +515,7 @@ int nem_step(nem_sim* s, int64_t nsteps) {
   if (!s || nsteps < 0) return NEM_E_INVAL;
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) { s->err = "nem_set_state was not called for every replica"; return NEM_E_STATE; }
-  const bool graph = s->use_graph && !s->timing;
-  if (graph && !s->graph[0]) {
-    int rc = capture_graphs(s);
-    if (rc) { drop_graphs(s); return rc; }
-  }
-  for (int64_t it = 0; it < nsteps; ++it) {
-    if (graph) {
-      HIPCHK(hipGraphLaunch(s->graph[s->parity], s->stream));
-    } else {
-      int rc = enqueue_step(s, s->stream);
-      if (rc) return rc;
-    }
-    s->parity ^= 1;
-  }
-  return NEM_OK;
+  return run_steps(s, nsteps);
 }
 
 int nem_sync(nem_sim* s) {
@@ -558,14 +569,27 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {
   if (!s || r < 0 || r >= s->R || !out) return NEM_E_INVAL;
   if (!s->has_state[r]) return NEM_E_STATE;
   SortArgs a = sort_args(s, nullptr);
-  launch_reduce(a, r, (int)s->n[r], s->red, s->stream);
+  // pair sums at the integer time level: integer-level offsets into the
+  // staging array, then pass A (volumes, neighbour list) and the free-energy
+  // kernel on them; the per-step temporaries are rebuilt by the next step
+  launch_int_offsets(a, s->t_off, s->stream);
+  StepArgs sa = step_args(s);
+  sa.off_cur = s->t_off;
+  const PassCfg cfg{s->T, 1, 1, 0, 0};
+  if (!launch_pass(1, cfg, sa, s->stream)) return NEM_E_INVAL;
+  launch_free_energy(s->T, sa, s->fe, s->stream);
+  launch_reduce(a, r, (int)s->n[r], s->fe, s->red, s->stream);
   HIPCHK(hipGetLastError());
   double h[8];
-  unsigned um = 0;
+  unsigned ums[UMAX_SLOTS];
   HIPCHK(hipMemcpyAsync(h, s->red, sizeof(double) * 8, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipMemcpyAsync(&um, s->umax + (size_t)(1 - s->parity) * s->R + r, sizeof(unsigned),
+  // c0 of the last step: its pass C read the slots of the parity before the flip
+  const int last = 1 - s->parity;
+  HIPCHK(hipMemcpyAsync(ums, s->umax + ((size_t)last * s->R + r) * UMAX_SLOTS, sizeof(ums),
                         hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned um = 0;
+  for (unsigned v : ums) um = std::max(um, v);
   const double m = s->hp[r].rho0 * s->hp[r].dx * s->hp[r].dx;
   float umf;
   std::memcpy(&umf, &um, sizeof(umf));
@@ -574,11 +598,73 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {
   out->ke = h[2] / (double)s->n[r];
   out->umax = h[3];
   out->qmax = h[4];
-  out->F = NAN;
-  out->F_grad = NAN;
+  out->F = h[5];
+  out->F_grad = h[6];
   out->c0 = s->hp[r].c0_factor * (double)umf;
   unsigned f[2];
   int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_deposit(nem_sim* s, int32_t r, int32_t M, double* out) {
+  if (!s || !out) return NEM_E_INVAL;
+  int rc = deposit_grid(s, r, M);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(out, s->g_grid, sizeof(double) * 4 * (size_t)M * M, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_spectrum(nem_sim* s, int32_t r, int32_t M, double* E, int32_t nbins, int32_t k_lo, int32_t k_hi,
+                 double* slope) {
+  if (!s || !E || nbins < 1) return NEM_E_INVAL;
+  int rc = deposit_grid(s, r, M);
+  if (rc) return rc;
+  int logM = 0;
+  while ((1 << logM) < M) ++logM;
+  launch_fft2(s->g_grid, s->g_z, s->g_w, M, logM, s->stream);
+  launch_shells(s->g_w, M, s->gbins, s->g_part, s->g_E, s->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(s->gbins);
+  HIPCHK(hipMemcpyAsync(h.data(), s->g_E, sizeof(double) * s->gbins, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (int n = 0; n < nbins; ++n) E[n] = n < s->gbins ? h[n] : 0.0;
+  if (slope) {
+    // least-squares slope of ln E against ln n over [k_lo, k_hi] (defaults 4, M/8)
+    const int lo = k_lo > 0 ? k_lo : 4, hi = k_hi > 0 ? k_hi : M / 8;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    int m = 0;
+    for (int n = lo; n <= hi && n < s->gbins; ++n) {
+      if (!(h[n] > 0)) continue;
+      const double x = std::log((double)n), y = std::log(h[n]);
+      sx += x; sy += y; sxx += x * x; sxy += x * y; ++m;
+    }
+    *slope = (m >= 2) ? (m * sxy - sx * sy) / (m * sxx - sx * sx) : NAN;
+  }
+  unsigned f[2];
+  rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus) {
+  if (!s || !n_plus || !n_minus) return NEM_E_INVAL;
+  int rc = deposit_grid(s, r, M);
+  if (rc) return rc;
+  HIPCHK(hipMemsetAsync(s->g_cnt, 0, sizeof(unsigned long long) * 2, s->stream));
+  launch_winding(s->g_grid, M, s->g_cnt, s->stream);
+  HIPCHK(hipGetLastError());
+  unsigned long long c[2];
+  HIPCHK(hipMemcpyAsync(c, s->g_cnt, sizeof(c), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *n_plus = (int64_t)c[0];
+  *n_minus = (int64_t)c[1];
+  unsigned f[2];
+  rc = read_flags(s, f);
   if (rc) return rc;
   return status_from_flags(s, f[0]);
 }
@@ -634,6 +720,8 @@ void nem_destroy(nem_sim* s) {
   for (auto& e : s->ev_free) hipEventDestroy(e);
   drop_graphs(s);
   if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+  free_grid(s);
+  free_snapshot(s);
   if (s->own && s->arena) hipFree(s->arena);
   delete s;
 }

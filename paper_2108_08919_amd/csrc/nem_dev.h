@@ -9,7 +9,8 @@ namespace nem {
 constexpr int WG = 256;          // threads per workgroup of every pair pass
 constexpr int MAXT = 8;          // largest tile side in cells
 constexpr int MAXSC = (MAXT + 2) * (MAXT + 2);  // staged cells per tile (interior + halo)
-constexpr int MAXS = 1536;       // staged particles per tile (LDS capacity)
+constexpr int KMAX = 64;         // accepted neighbours per particle (list capacity)
+constexpr int UMAX_SLOTS = 64;   // per-replica slots of the max-speed reduction
 
 // Sticky device error bits (flags[0]).
 enum : unsigned {
@@ -46,6 +47,7 @@ struct StepArgs {
   const RepDev* reps;
   const int* work;        // 2 ints per work item: replica, tile index
   int nwork, T;           // work items, tile side in cells
+  int lpp;                // lanes per particle in passes B-D (1, 2, 4)
   const int* cell_start;  // [ncells + 1], particles sorted by (replica, cell, id)
   int ncells, ntot;
   const float2* off_cur;  // cell-relative position (high part) at r^{n+1/2}
@@ -66,8 +68,14 @@ struct StepArgs {
   float* P;               // p / rho_hat^2
   float* drhat;           // rho_hat - rho0
   unsigned* flags;        // [0] error bits, [1] rebin request
-  const unsigned* umax_cur;  // per replica: max |u^{n+1/2}| (float bits)
-  unsigned* umax_nxt;        // per replica: max |u^{n+3/2}| being accumulated
+  const unsigned* umax_cur;  // [R][UMAX_SLOTS]: max |u^{n+1/2}| (float bits)
+  unsigned* umax_nxt;        // [R][UMAX_SLOTS]: max |u^{n+3/2}| being accumulated
+  uint32_t* nl;              // neighbour list: word w of particle g at nl[w*ntot + g],
+                             // two 16-bit entries (LDS slot | (dx+1)<<12 | (dy+1)<<14)
+  int* ncnt;                 // accepted neighbours per particle
+  float4* apdg;              // APD geometry: (sum rx/r^3, sum ry/r^3, sum r, count)
+  float* feat;               // NULL, or 12 features per particle at [part_base + id]
+  const int* id;             // particle ids (sorted order)
 };
 
 // Kernel variant of the pair passes.
@@ -99,6 +107,12 @@ void launch_rebin_key(const SortArgs& s, hipStream_t st);
 void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base, hipStream_t st);
 void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st);
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st);
-void launch_reduce(const SortArgs& s, int r, int n, double* red, hipStream_t st);
+void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* red, hipStream_t st);
+void launch_free_energy(int T, const StepArgs& a, double* fe, hipStream_t s);
+void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st);
+void launch_deposit(int T, const StepArgs& a, int rep, int M, double* grid, hipStream_t s);
+void launch_fft2(const double* grid, double2* z, double2* w, int M, int logM, hipStream_t s);
+void launch_shells(const double2* Z, int M, int nbins, double* part, double* E, hipStream_t s);
+void launch_winding(const double* grid, int M, unsigned long long* counts, hipStream_t s);
 
 }  // namespace nem

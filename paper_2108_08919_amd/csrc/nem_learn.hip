@@ -1,0 +1,520 @@
+// nem_learn.hip -- the learned corrector: training samples drawn from the
+// solver itself, the network's training loop, and macro steps of mult*dt whose
+// Q and u are corrected by the network, with fine steps as the fallback.
+//
+// A macro step: take one step with time step mult*dt from the current state
+// while pass B writes each particle's 12 inputs (Q, grad u, H, density,
+// activity), run the network on them, and add the predicted corrections
+// (dQxx, dQxy, dQyy, dux, duy) to Q and u. If the largest correction (in the
+// network's normalised units) exceeds tau, the macro step is discarded and
+// replayed from a device snapshot as mult steps of dt. Training targets are the
+// difference between mult steps of dt and one step of mult*dt from the same
+// state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "nem_dev.h"
+#include "nem_sim.h"
+
+namespace nem {
+
+int mlp_nparam();
+int mlp_backward_waves(int64_t B);
+void launch_mlp_forward(const float* P, const float* norm, const float* X, int64_t n, float* Y, unsigned* maxnorm,
+                        hipStream_t s);
+void launch_mlp_backward(const float* P, const float* norm, const float* X, const float* T, const int64_t* idx,
+                         int64_t B, float* partial, float* lossp, int nwaves, hipStream_t s);
+void launch_mlp_reduce(const float* partial, int nw, float* grads, const float* lossp, float* loss, hipStream_t s);
+void launch_mlp_adam(float* P, const float* g, float* m, float* v, float lr, int t, hipStream_t s);
+void launch_mlp_batch(int64_t* idx, int64_t first, int64_t B, int64_t n, int64_t stride, int64_t offset,
+                      hipStream_t s);
+void launch_mlp_stats(const float* X, const float* T, int64_t n, double* out, hipStream_t s);
+
+__device__ inline int rep_of(const RepDev* reps, int R, int k) {
+  int lo = 0, hi = R;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (reps[mid].part_base <= k) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Change every replica's time step by `factor`: recover r^n, u^n from the
+// stored prediction (made with the old dt) and predict again with the new dt.
+// Positions move by a few rounding units at most; the max-speed slots of the
+// current parity are refilled (cleared by the caller).
+__global__ void k_repredict(SortArgs s, float factor, unsigned* umax_cur) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of(s.reps, s.R, k);
+    const float dto = s.reps[r].dt, dtn = dto * factor;
+    const float2 u = s.u[k], ac = s.acc[k], o = s.off[k], lo = s.offlo[k];
+    const float unx = (u.x - 0.5f * dto * ac.x) + 0.5f * dtn * ac.x;
+    const float uny = (u.y - 0.5f * dto * ac.y) + 0.5f * dtn * ac.y;
+    const float dx = 0.5f * dtn * unx - 0.5f * dto * u.x, dy = 0.5f * dtn * uny - 0.5f * dto * u.y;
+    float2 nh, nl;
+    {
+#pragma clang fp contract(off)
+      float t = o.x + dx, bp = t - o.x, e = (o.x - (t - bp)) + (dx - bp), l2 = lo.x + e;
+      nh.x = t + l2; nl.x = l2 - (nh.x - t);
+      t = o.y + dy; bp = t - o.y; e = (o.y - (t - bp)) + (dy - bp); l2 = lo.y + e;
+      nh.y = t + l2; nl.y = l2 - (nh.y - t);
+    }
+    s.off[k] = nh;
+    s.offlo[k] = nl;
+    s.u[k] = make_float2(unx, uny);
+    atomicMax(&umax_cur[r * UMAX_SLOTS + (k & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(unx * unx + uny * uny)));
+  }
+}
+
+// (Qxx, Qxy, Qyy, ux, uy) at the integer level into out[(part_base + id) * 5].
+__global__ void k_export_qu(SortArgs s, float* out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of(s.reps, s.R, k);
+    const RepDev& R = s.reps[r];
+    const int id = s.id[k];
+    if (id < 0 || id >= R.n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const float2 q = s.q[k], u = s.u[k], ac = s.acc[k];
+    float* o = out + (size_t)(R.part_base + id) * 5;
+    o[0] = q.x; o[1] = q.y; o[2] = -q.x;
+    o[3] = u.x - 0.5f * R.dt * ac.x;
+    o[4] = u.y - 0.5f * R.dt * ac.y;
+  }
+}
+
+__global__ void k_sub(float* T, const float* C, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    T[k] -= C[k];
+}
+
+// Add the network's corrections Y[(part_base + id) * 5] to Q (projected on
+// traceless tensors) and u; refill the max-speed slots (cleared by the caller).
+__global__ void k_correct(SortArgs s, const float* Y, unsigned* umax_cur) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of(s.reps, s.R, k);
+    const RepDev& R = s.reps[r];
+    const int id = s.id[k];
+    if (id < 0 || id >= R.n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const float* y = Y + (size_t)(R.part_base + id) * 5;
+    float2 q = s.q[k], u = s.u[k];
+    q.x += 0.5f * (y[0] - y[2]);
+    q.y += y[1];
+    u.x += y[3];
+    u.y += y[4];
+    s.q[k] = q;
+    s.u[k] = u;
+    // the stored position is r^{n+1} + u dt/2: move it with the corrected u
+    const float dx = 0.5f * R.dt * y[3], dy = 0.5f * R.dt * y[4];
+    const float2 o = s.off[k], lo = s.offlo[k];
+    float2 nh, nl;
+    {
+#pragma clang fp contract(off)
+      float t = o.x + dx, bp = t - o.x, e = (o.x - (t - bp)) + (dx - bp), l2 = lo.x + e;
+      nh.x = t + l2; nl.x = l2 - (nh.x - t);
+      t = o.y + dy; bp = t - o.y; e = (o.y - (t - bp)) + (dy - bp); l2 = lo.y + e;
+      nh.y = t + l2; nl.y = l2 - (nh.y - t);
+    }
+    s.off[k] = nh;
+    s.offlo[k] = nl;
+    atomicMax(&umax_cur[r * UMAX_SLOTS + (k & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(u.x * u.x + u.y * u.y)));
+  }
+}
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+}  // namespace nem
+
+using namespace nem;
+using namespace nem_host;
+
+struct nem_mlp {
+  hipStream_t stream = nullptr;
+  float* P = nullptr;      // FP32 master weights
+  float* m = nullptr;      // Adam moments
+  float* v = nullptr;
+  float* g = nullptr;      // gradient
+  float* norm = nullptr;   // x mean[12], x std[12], y mean[5], y std[5] (device)
+  float hnorm[34];
+  float* partial = nullptr;
+  float* lossp = nullptr;
+  float* loss = nullptr;
+  int64_t* idx = nullptr;
+  int64_t idx_cap = 0;
+  int part_waves = 0;
+  double* stats = nullptr;
+  int adam_t = 0;
+  std::string err;
+};
+
+namespace nem_host {
+
+void free_snapshot(nem_sim* s) {
+  auto& S = s->snap;
+  for (void* p : {(void*)S.off, (void*)S.offlo, (void*)S.u, (void*)S.q, (void*)S.acc, (void*)S.drho, (void*)S.id,
+                  (void*)S.cell, (void*)S.cell_start, (void*)S.umax})
+    if (p) hipFree(p);
+  S = nem_sim::Snap();
+}
+
+static int take_snapshot(nem_sim* s) {
+  auto& S = s->snap;
+  const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
+  if (!S.alloc) {
+    HIPCHK(hipMalloc((void**)&S.off, sizeof(float2) * N));
+    HIPCHK(hipMalloc((void**)&S.offlo, sizeof(float2) * N));
+    HIPCHK(hipMalloc((void**)&S.u, sizeof(float2) * N));
+    HIPCHK(hipMalloc((void**)&S.q, sizeof(float2) * N));
+    HIPCHK(hipMalloc((void**)&S.acc, sizeof(float2) * N));
+    HIPCHK(hipMalloc((void**)&S.drho, sizeof(float) * N));
+    HIPCHK(hipMalloc((void**)&S.id, sizeof(int) * N));
+    HIPCHK(hipMalloc((void**)&S.cell, sizeof(int) * N));
+    HIPCHK(hipMalloc((void**)&S.cell_start, sizeof(int) * (C + 1)));
+    HIPCHK(hipMalloc((void**)&S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS));
+    S.alloc = true;
+  }
+  const int p = s->parity;
+  const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+  HIPCHK(hipMemcpyAsync(S.off, s->off[p], sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.offlo, s->offlo, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.u, s->u, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.q, s->q[p], sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.acc, s->acc, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.drho, s->drho, sizeof(float) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.id, s->id, sizeof(int) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.cell, s->cell, sizeof(int) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.cell_start, s->cell_start, sizeof(int) * (C + 1), d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(S.umax, s->umax + (size_t)p * s->R * UMAX_SLOTS, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
+                        s->stream));
+  HIPCHK(hipMemcpyAsync(S.flags, s->flags, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  S.parity = p;
+  S.dt.resize(s->R);
+  for (int r = 0; r < s->R; ++r) S.dt[r] = s->reps[r].dt;
+  S.valid = true;
+  return NEM_OK;
+}
+
+static int restore_snapshot(nem_sim* s) {
+  auto& S = s->snap;
+  if (!S.valid) return NEM_E_STATE;
+  const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
+  const int p = S.parity;
+  const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+  HIPCHK(hipMemcpyAsync(s->off[p], S.off, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->offlo, S.offlo, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->u, S.u, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->q[p], S.q, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->acc, S.acc, sizeof(float2) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->drho, S.drho, sizeof(float) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->id, S.id, sizeof(int) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->cell, S.cell, sizeof(int) * N, d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->cell_start, S.cell_start, sizeof(int) * (C + 1), d2d, s->stream));
+  HIPCHK(hipMemcpyAsync(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
+                        s->stream));
+  // keep the sticky error bits, restore the rebin request
+  unsigned f[2];
+  HIPCHK(hipMemcpyAsync(f, s->flags, sizeof(f), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  f[1] = S.flags[1];
+  HIPCHK(hipMemcpyAsync(s->flags, f, sizeof(f), hipMemcpyHostToDevice, s->stream));
+  s->parity = p;
+  for (int r = 0; r < s->R; ++r) s->reps[r].dt = S.dt[r];
+  int rc = upload_reps(s);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return NEM_OK;
+}
+
+// Scale every replica's dt by `factor` and re-predict the stored state.
+static int scale_dt(nem_sim* s, float factor) {
+  unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
+  HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream));
+  SortArgs a = sort_args(s, nullptr);
+  hipLaunchKernelGGL(k_repredict, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, factor, um);
+  HIPCHK(hipGetLastError());
+  for (auto& R : s->reps) R.dt *= factor;
+  return upload_reps(s);
+}
+
+static int check_flags(nem_sim* s) {
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+}  // namespace nem_host
+
+static int mlp_fail(nem_mlp* m, hipError_t e, const char* what) {
+  m->err = std::string(what) + ": " + hipGetErrorString(e);
+  return NEM_E_HIP;
+}
+#define MLPCHK(expr)                                      \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return mlp_fail(m, e_, #expr);  \
+  } while (0)
+
+static int mlp_ensure_idx(nem_mlp* m, int64_t B) {
+  if (m->idx_cap >= B) return NEM_OK;
+  if (m->idx) hipFree(m->idx);
+  m->idx = nullptr;
+  MLPCHK(hipMalloc((void**)&m->idx, sizeof(int64_t) * B));
+  m->idx_cap = B;
+  return NEM_OK;
+}
+
+static int mlp_ensure_partial(nem_mlp* m, int nw) {
+  if (m->part_waves >= nw) return NEM_OK;
+  if (m->partial) hipFree(m->partial);
+  if (m->lossp) hipFree(m->lossp);
+  m->partial = nullptr; m->lossp = nullptr;
+  MLPCHK(hipMalloc((void**)&m->partial, sizeof(float) * (size_t)nw * mlp_nparam()));
+  MLPCHK(hipMalloc((void**)&m->lossp, sizeof(float) * nw));
+  m->part_waves = nw;
+  return NEM_OK;
+}
+
+// Gradient of the mean loss over the index map m->idx[0..B) into m->g.
+static int mlp_grad_batch(nem_mlp* m, const float* X, const float* T, int64_t B) {
+  const int nw = mlp_backward_waves(B);
+  int rc = mlp_ensure_partial(m, nw);
+  if (rc) return rc;
+  launch_mlp_backward(m->P, m->hnorm, X, T, m->idx, B, m->partial, m->lossp, nw, m->stream);
+  launch_mlp_reduce(m->partial, nw, m->g, m->lossp, m->loss, m->stream);
+  MLPCHK(hipGetLastError());
+  return NEM_OK;
+}
+
+extern "C" {
+
+int nem_mlp_nparams(void) { return mlp_nparam(); }
+
+int nem_mlp_create(void* hip_stream, nem_mlp** out) {
+  if (!out) return NEM_E_INVAL;
+  nem_mlp* m = new nem_mlp();
+  m->stream = (hipStream_t)hip_stream;
+  const int np = mlp_nparam();
+  bool ok = hipMalloc((void**)&m->P, sizeof(float) * np) == hipSuccess &&
+            hipMalloc((void**)&m->m, sizeof(float) * np) == hipSuccess &&
+            hipMalloc((void**)&m->v, sizeof(float) * np) == hipSuccess &&
+            hipMalloc((void**)&m->g, sizeof(float) * np) == hipSuccess &&
+            hipMalloc((void**)&m->norm, sizeof(float) * 34) == hipSuccess &&
+            hipMalloc((void**)&m->loss, sizeof(float)) == hipSuccess &&
+            hipMalloc((void**)&m->stats, sizeof(double) * 34) == hipSuccess;
+  if (!ok) { nem_mlp_destroy(m); return NEM_E_NOMEM; }
+  for (int i = 0; i < 12; ++i) { m->hnorm[i] = 0.0f; m->hnorm[12 + i] = 1.0f; }
+  for (int i = 0; i < 5; ++i) { m->hnorm[24 + i] = 0.0f; m->hnorm[29 + i] = 1.0f; }
+  hipMemsetAsync(m->P, 0, sizeof(float) * np, m->stream);
+  hipMemsetAsync(m->m, 0, sizeof(float) * np, m->stream);
+  hipMemsetAsync(m->v, 0, sizeof(float) * np, m->stream);
+  hipMemcpyAsync(m->norm, m->hnorm, sizeof(m->hnorm), hipMemcpyHostToDevice, m->stream);
+  if (hipStreamSynchronize(m->stream) != hipSuccess) { nem_mlp_destroy(m); return NEM_E_HIP; }
+  *out = m;
+  return NEM_OK;
+}
+
+int nem_mlp_set_weights(nem_mlp* m, const float* w) {
+  if (!m || !w) return NEM_E_INVAL;
+  const int np = mlp_nparam();
+  MLPCHK(hipMemcpyAsync(m->P, w, sizeof(float) * np, hipMemcpyHostToDevice, m->stream));
+  MLPCHK(hipMemsetAsync(m->m, 0, sizeof(float) * np, m->stream));
+  MLPCHK(hipMemsetAsync(m->v, 0, sizeof(float) * np, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  m->adam_t = 0;
+  return NEM_OK;
+}
+
+int nem_mlp_get_weights(nem_mlp* m, float* w) {
+  if (!m || !w) return NEM_E_INVAL;
+  MLPCHK(hipMemcpyAsync(w, m->P, sizeof(float) * mlp_nparam(), hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  return NEM_OK;
+}
+
+int nem_mlp_set_norm(nem_mlp* m, const float* norm) {
+  if (!m || !norm) return NEM_E_INVAL;
+  for (int i = 0; i < 34; ++i) m->hnorm[i] = norm[i];
+  for (int i = 12; i < 24; ++i) if (!(m->hnorm[i] > 0)) m->hnorm[i] = 1.0f;
+  for (int i = 29; i < 34; ++i) if (!(m->hnorm[i] > 0)) m->hnorm[i] = 1.0f;
+  MLPCHK(hipMemcpyAsync(m->norm, m->hnorm, sizeof(m->hnorm), hipMemcpyHostToDevice, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  return NEM_OK;
+}
+
+int nem_mlp_get_norm(nem_mlp* m, float* norm) {
+  if (!m || !norm) return NEM_E_INVAL;
+  std::memcpy(norm, m->hnorm, sizeof(m->hnorm));
+  return NEM_OK;
+}
+
+int nem_mlp_fit_norm(nem_mlp* m, const float* X, const float* T, int64_t n) {
+  if (!m || !X || !T || n < 2) return NEM_E_INVAL;
+  launch_mlp_stats(X, T, n, m->stats, m->stream);
+  MLPCHK(hipGetLastError());
+  double st[34];
+  MLPCHK(hipMemcpyAsync(st, m->stats, sizeof(st), hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  float nm[34];
+  for (int c = 0; c < 12; ++c) { nm[c] = (float)st[2 * c]; nm[12 + c] = (float)st[2 * c + 1]; }
+  for (int c = 0; c < 5; ++c) { nm[24 + c] = (float)st[2 * (12 + c)]; nm[29 + c] = (float)st[2 * (12 + c) + 1]; }
+  // constant inputs (zero spread) are passed through unscaled
+  for (int i = 12; i < 24; ++i) if (!(nm[i] > 1e-30f)) nm[i] = 1.0f;
+  for (int i = 29; i < 34; ++i) if (!(nm[i] > 1e-30f)) nm[i] = 1.0f;
+  return nem_mlp_set_norm(m, nm);
+}
+
+int nem_mlp_forward(nem_mlp* m, const float* X, int64_t n, float* Y) {
+  if (!m || !X || !Y || n < 1) return NEM_E_INVAL;
+  launch_mlp_forward(m->P, m->hnorm, X, n, Y, nullptr, m->stream);
+  MLPCHK(hipGetLastError());
+  MLPCHK(hipStreamSynchronize(m->stream));
+  return NEM_OK;
+}
+
+int nem_mlp_grad(nem_mlp* m, const float* X, const float* T, int64_t n, float* grad, double* loss) {
+  if (!m || !X || !T || !grad || n < 1) return NEM_E_INVAL;
+  int rc = mlp_ensure_idx(m, n);
+  if (rc) return rc;
+  launch_mlp_batch(m->idx, 0, n, n, 1, 0, m->stream);
+  rc = mlp_grad_batch(m, X, T, n);
+  if (rc) return rc;
+  float l = 0.f;
+  MLPCHK(hipMemcpyAsync(grad, m->g, sizeof(float) * mlp_nparam(), hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(hipMemcpyAsync(&l, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  if (loss) *loss = l;
+  return NEM_OK;
+}
+
+int nem_mlp_train(nem_mlp* m, const float* X, const float* T, int64_t n, int32_t epochs, int32_t batch, double lr,
+                  double* final_loss) {
+  if (!m || !X || !T || n < 1 || epochs < 1 || batch < 32) return NEM_E_INVAL;
+  const int64_t B = std::min<int64_t>(batch, n);
+  int rc = mlp_ensure_idx(m, B);
+  if (rc) return rc;
+  // per-epoch shuffle: idx = (k * stride + offset) mod n with stride coprime to n
+  auto gcd = [](int64_t a, int64_t b) { while (b) { int64_t t = a % b; a = b; b = t; } return a; };
+  int64_t stride = (int64_t)(0.6180339887 * (double)n) | 1;
+  while (gcd(stride, n) != 1) stride += 2;
+  double last = 0.0;
+  for (int e = 0; e < epochs; ++e) {
+    const int64_t offset = (int64_t)((uint64_t)(e + 1) * 2654435761ull % (uint64_t)n);
+    for (int64_t first = 0; first + B <= n; first += B) {
+      launch_mlp_batch(m->idx, first, B, n, stride % n, offset, m->stream);
+      rc = mlp_grad_batch(m, X, T, B);
+      if (rc) return rc;
+      ++m->adam_t;
+      launch_mlp_adam(m->P, m->g, m->m, m->v, (float)lr, m->adam_t, m->stream);
+    }
+    MLPCHK(hipGetLastError());
+  }
+  float l = 0.f;
+  MLPCHK(hipMemcpyAsync(&l, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(hipStreamSynchronize(m->stream));
+  last = l;
+  if (final_loss) *final_loss = last;
+  return NEM_OK;
+}
+
+void nem_mlp_destroy(nem_mlp* m) {
+  if (!m) return;
+  if (m->stream) hipStreamSynchronize(m->stream);
+  for (void* p : {(void*)m->P, (void*)m->m, (void*)m->v, (void*)m->g, (void*)m->norm, (void*)m->partial,
+                  (void*)m->lossp, (void*)m->loss, (void*)m->idx, (void*)m->stats})
+    if (p) hipFree(p);
+  delete m;
+}
+
+int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
+  if (!s || mult < 2 || !X || !T) return NEM_E_INVAL;
+  for (int r = 0; r < s->R; ++r)
+    if (!s->has_state[r]) return NEM_E_STATE;
+  int rc = take_snapshot(s);
+  if (rc) return rc;
+  float* coarse = nullptr;
+  HIPCHK(hipMalloc((void**)&coarse, sizeof(float) * 5 * (size_t)s->ntot));
+  // one step of mult*dt with the inputs captured
+  rc = scale_dt(s, (float)mult);
+  if (!rc) {
+    s->feat = X;
+    rc = run_steps(s, 1);
+    s->feat = nullptr;
+  }
+  if (!rc) {
+    SortArgs a = sort_args(s, nullptr);
+    hipLaunchKernelGGL(k_export_qu, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, coarse);
+  }
+  // mult steps of dt from the same state
+  if (!rc) rc = restore_snapshot(s);
+  if (!rc) rc = run_steps(s, mult);
+  if (!rc) {
+    SortArgs a = sort_args(s, nullptr);
+    hipLaunchKernelGGL(k_export_qu, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, T);
+    hipLaunchKernelGGL(k_sub, dim3(grid_for(5 * (int64_t)s->ntot)), dim3(256), 0, s->stream, T, coarse,
+                       5 * (int64_t)s->ntot);
+  }
+  if (!rc) rc = restore_snapshot(s);
+  hipStreamSynchronize(s->stream);
+  hipFree(coarse);
+  if (rc) return rc;
+  return check_flags(s);
+}
+
+int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, double tau, int64_t* n_fallback,
+                     double* max_norm) {
+  if (!s || !m || n_macro < 0 || mult < 2 || !(tau > 0)) return NEM_E_INVAL;
+  for (int r = 0; r < s->R; ++r)
+    if (!s->has_state[r]) return NEM_E_STATE;
+  const size_t N = (size_t)s->ntot;
+  float *X = nullptr, *Y = nullptr;
+  unsigned* mx = nullptr;
+  HIPCHK(hipMalloc((void**)&X, sizeof(float) * 12 * N));
+  HIPCHK(hipMalloc((void**)&Y, sizeof(float) * 5 * N));
+  HIPCHK(hipMalloc((void**)&mx, sizeof(unsigned)));
+  int64_t nfb = 0;
+  float worst = 0.0f;
+  int rc = scale_dt(s, (float)mult);
+  for (int64_t it = 0; it < n_macro && !rc; ++it) {
+    rc = take_snapshot(s);
+    if (rc) break;
+    s->feat = X;
+    rc = run_steps(s, 1);
+    s->feat = nullptr;
+    if (rc) break;
+    HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), s->stream));
+    launch_mlp_forward(m->P, m->hnorm, X, (int64_t)N, Y, mx, s->stream);
+    unsigned hm = 0;
+    HIPCHK(hipMemcpyAsync(&hm, mx, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    float fm;
+    std::memcpy(&fm, &hm, sizeof(fm));
+    worst = std::max(worst, fm);
+    if (!(fm <= (float)tau)) {
+      // discard: replay the macro step as mult steps of dt
+      ++nfb;
+      rc = restore_snapshot(s);
+      if (!rc) rc = scale_dt(s, 1.0f / (float)mult);
+      if (!rc) rc = run_steps(s, mult);
+      if (!rc) rc = scale_dt(s, (float)mult);
+      continue;
+    }
+    unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
+    HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream));
+    SortArgs a = sort_args(s, nullptr);
+    hipLaunchKernelGGL(k_correct, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, Y, um);
+    HIPCHK(hipGetLastError());
+  }
+  if (!rc) rc = scale_dt(s, 1.0f / (float)mult);
+  hipStreamSynchronize(s->stream);
+  hipFree(X); hipFree(Y); hipFree(mx);
+  if (n_fallback) *n_fallback = nfb;
+  if (max_norm) *max_norm = worst;
+  if (rc) return rc;
+  return check_flags(s);
+}
+
+}  // extern "C"

@@ -159,6 +159,8 @@ struct Acc {
   __device__ __forceinline__ void end_cell() {
     if constexpr (COMP == 1) { kahan(s, c, p); p = 0.0f; }
   }
+  // This lane's compensated value.
+  __device__ __forceinline__ float value() const { return (COMP == 0) ? s : (s - c); }
   // Value summed over the LPP lanes that share a particle.
   template <int LPP>
   __device__ __forceinline__ float total() const {
@@ -170,5 +172,30 @@ struct Acc {
 };
 
 __device__ __forceinline__ void flag(unsigned* flags, unsigned bit) { atomicOr(flags, bit); }
+
+// Common prologue: set up the tile, check LDS capacity. Returns false when the
+// workgroup has nothing to do (uniform across the workgroup).
+template <int T>
+__device__ __forceinline__ bool tile_begin(const StepArgs& a, TileLDS<T>& L, RepDev& R, int& rep) {
+  const int w = blockIdx.x;
+  if (w >= a.nwork) return false;
+  rep = tile_setup<T>(a, w, L, R);
+  const int S = L.cstart[L.hdr[3]];
+  if (S > TileCfg<T>::MAXP) {
+    if (threadIdx.x == 0) flag(a.flags, ERR_OVERFLOW);
+    return false;
+  }
+  return true;
+}
+
+// Global index of LDS slot t (staging loop).
+template <int T>
+__device__ __forceinline__ int staged_global(const StepArgs& a, const TileLDS<T>& L, int t) {
+  const int st = find_cell(L.cstart, L.hdr[3], t);
+  int g = L.gstart[st] + (t - L.cstart[st]);
+  if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = 0; }
+  return g;
+}
+
 
 }  // namespace nem

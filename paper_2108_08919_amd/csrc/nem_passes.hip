@@ -1,58 +1,92 @@
 // nem_passes.hip -- the four pair passes of one SPH time step on gfx950.
 //
-// Each workgroup owns a tile of T x T cells of one replica, stages the tile and
-// its one-cell periodic halo into LDS (particles are sorted by cell, so every
-// cell is a contiguous run), and lets LPP lanes cooperate on each interior
-// particle: lane `sub` takes every LPP-th candidate of each stencil cell and
-// the lane sums are combined with wave shuffles. Positions are FP32 offsets
-// from the particle's cell corner; the periodic image shift of a stencil cell
-// is a whole number of cell sides, so pair vectors keep the precision of the
-// offsets anywhere in the box.
+// Each workgroup owns a tile of T x T cells of one replica and stages the tile
+// plus its one-cell periodic halo into LDS (particles are sorted by cell, so
+// every cell is a contiguous run). Positions are FP32 offsets from the
+// particle's cell corner; the periodic image shift of a stencil cell is a whole
+// number of cell sides, so pair vectors keep the precision of the offsets
+// anywhere in the box.
 //
-//   pass A  volume V_i = 1 / sum_j W_ij (Eq. sphSum, self included)
+// Pass A tests the ~144 candidates of the 3 x 3 cell stencil once per step and
+// keeps, per particle, the accepted neighbours as 16-bit entries (LDS slot of
+// the neighbour in the tile's staging order + stencil direction). Passes B, C
+// and D stage the same tile in the same order and walk that list, so they do
+// no candidate rejection. Several lanes may share a particle (each takes every
+// lpp-th neighbour; sums are combined with wave shuffles); a tile's short tail
+// of particles is spread over more lanes.
+//
+//   pass A  neighbour list; volume V_i = 1 / sum_j W_ij (Eq. sphSum, self
+//           included); APD geometry sums (Eq. APD)
 //   pass B  correction tensor and B = alpha^{-1} (Eq. sphCorrectionMatrix),
 //           velocity gradient and continuity (Eqs. sph1stDerivative,
 //           sphContinuity), Q gradient and Laplacian, molecular field
 //           (Eq. molecularfielddis), co-rotation (Eq. corotation), Q update
-//           (Eq. mi), viscous and active accelerations (Eq. sphMomentum),
-//           APD velocity variance (Eq. APD)
+//           (Eq. mi), viscous and active accelerations (Eq. sphMomentum), APD
+//           velocity variance (Eq. APD)
 //   pass C  density filter (Eq. densityCorrection) and EoS (Eq. sphEos)
-//   pass D  pressure term (Eq. sphMomentum), corrector, APD (Eq. APD),
-//           and the next step's predictor (Sec. 3.1), fused
+//   pass D  pressure term (Eq. sphMomentum), corrector, APD displacement
+//           (Eq. APD) and the next step's predictor (Sec. 3.1), fused
 #include "nem_dev.h"
 #include "nem_pair.h"
 
 namespace nem {
 
-// Common prologue: set up the tile, check LDS capacity. Returns false when the
-// workgroup has nothing to do.
-template <int T>
-__device__ __forceinline__ bool tile_begin(const StepArgs& a, TileLDS<T>& L, RepDev& R, int& rep) {
-  const int w = blockIdx.x;
-  if (w >= a.nwork) return false;
-  rep = tile_setup<T>(a, w, L, R);
-  const int S = L.cstart[L.hdr[3]];
-  if (S > TileCfg<T>::MAXP) {
-    if (threadIdx.x == 0) flag(a.flags, ERR_OVERFLOW);
-    return false;
-  }
-  return true;
+// Lanes per particle for an iteration with `rem` particles left: the base
+// value, doubled while the particles still fill the workgroup (at most 16).
+__device__ __forceinline__ int lanes_for(int rem, int base_lpp) {
+  int l = base_lpp;
+  while (l < 16 && rem * l * 2 <= WG) l <<= 1;
+  return l;
 }
 
-// Global index of LDS slot t (staging loop).
-template <int T>
-__device__ __forceinline__ int staged_global(const StepArgs& a, const TileLDS<T>& L, int t) {
-  const int st = find_cell(L.cstart, L.hdr[3], t);
-  int g = L.gstart[st] + (t - L.cstart[st]);
-  if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = 0; }
-  return g;
+__device__ __forceinline__ float wave_sum(float v, int lpp) {
+  for (int o = 1; o < lpp; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Pair geometry of a listed neighbour: same operations as the predicate, so the
+// vector and r^2 are bit-identical to those pass A accepted.
+__device__ __forceinline__ void listed_pair(uint32_t e, float cs, int jmax, const float2* s_off, float2 oi,
+                                            int& j, float& rx, float& ry, float& r2) {
+  j = min((int)(e & 0xFFFu), jmax);
+  const float sx = (float)(1 - (int)((e >> 12) & 3u)) * cs;
+  const float sy = (float)(1 - (int)((e >> 14) & 3u)) * cs;
+  const float2 oj = s_off[j];
+  pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, 3.4e38f, rx, ry, r2);
+}
+
+// Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
+// sub, sub+lpp, ...; flush() closes a compensation chunk every 8 pairs.
+template <typename Body, typename Flush>
+__device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int ntot, int g, int cnt, int lpp,
+                                            int sub, Body&& body, Flush&& flush) {
+  const uint32_t* p = nl + g;
+  if (lpp == 1) {
+    int k = 0;
+    for (; k + 1 < cnt; k += 2) {
+      const uint32_t w = p[(size_t)(k >> 1) * ntot];
+      body(w & 0xFFFFu);
+      body(w >> 16);
+      if ((k & 7) == 6) flush();
+    }
+    if (k < cnt) body(p[(size_t)(k >> 1) * ntot] & 0xFFFFu);
+  } else {
+    int it = 0;
+    for (int k = sub; k < cnt; k += lpp, ++it) {
+      const uint32_t w = p[(size_t)(k >> 1) * ntot];
+      body((k & 1) ? (w >> 16) : (w & 0xFFFFu));
+      if ((it & 7) == 7) flush();
+    }
+  }
+  flush();
 }
 
 // ------------------------------------------------------------------ pass A
-template <int T, int LPP, int COMP>
+template <int T, int COMP>
 __global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T>::MAXP];
+  __shared__ uint32_t s_list[(KMAX / 2) * WG];  // lane-private list words, lane-major
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, L, R, rep)) return;
@@ -61,42 +95,56 @@ __global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
   for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
   __syncthreads();
   const int nin = L.cstart[nint];
-  const int sub = threadIdx.x % LPP;
-  for (int base = 0; base < nin; base += WG / LPP) {
-    const int p = base + threadIdx.x / LPP;
-    const bool act = p < nin;
-    int st = 0;
-    Acc<COMP> sw;
-    sw.init();
-    if (act) {
-      st = find_cell(L.cstart, nint, p);
-      const int li = st % ni, lj = st / ni;
-      const float2 oi = s_off[p];
+  const int tid = threadIdx.x;
+  for (int base = 0; base < nin; base += WG) {
+    const int p = base + tid;
+    if (p >= nin) break;
+    const int st = find_cell(L.cstart, nint, p);
+    const int li = st % ni, lj = st / ni;
+    const float2 oi = s_off[p];
+    Acc<COMP> sw, sx3, sy3, sr;
+    sw.init(); sx3.init(); sy3.init(); sr.init();
+    int cnt = 0;
+    uint32_t pend = 0;
 #pragma unroll 1
-      for (int cidx = 0; cidx < 9; ++cidx) {
-          const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
-          const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-          const int j1 = L.cstart[sc + 1];
-          const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-          for (int j = L.cstart[sc] + sub; j < j1; j += LPP) {
-            const float2 oj = s_off[j];
-            float rx, ry, r2;
-            if (pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) sw.add(quintic_W(R, r2));
-          }
-          sw.end_cell();
+    for (int cidx = 0; cidx < 9; ++cidx) {
+      const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
+      const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
+      const int j1 = L.cstart[sc + 1];
+      const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
+      const uint32_t dir = ((uint32_t)(dx + 1) << 12) | ((uint32_t)(dy + 1) << 14);
+      for (int j = L.cstart[sc]; j < j1; ++j) {
+        const float2 oj = s_off[j];
+        float rx, ry, r2;
+        if (!pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) continue;
+        const KW k = quintic(R, r2);
+        sw.add(k.W);
+        const float r3 = k.rinv * k.rinv * k.rinv;
+        sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(k.r);
+        const uint32_t e = (uint32_t)j | dir;
+        if (cnt < KMAX) {
+          if (cnt & 1) s_list[(cnt >> 1) * WG + tid] = pend | (e << 16);
+          else pend = e;
         }
+        ++cnt;
+      }
+      sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
     }
-    const float tot = sw.template total<LPP>();
-    if (act && sub == 0) {
-      const int g = L.gstart[st] + (p - L.cstart[st]);
-      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
-      a.V[g] = 1.0f / (R.W0 + tot);
-    }
+    const int kept = min(cnt, KMAX);
+    if (kept & 1) s_list[(kept >> 1) * WG + tid] = pend;
+    const int g = L.gstart[st] + (p - L.cstart[st]);
+    if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
+    if (cnt > KMAX) flag(a.flags, ERR_OVERFLOW);
+    a.V[g] = 1.0f / (R.W0 + sw.value());
+    a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)kept);
+    a.ncnt[g] = kept;
+    uint32_t* dst = a.nl + g;
+    for (int w = 0; w < ((kept + 1) >> 1); ++w) dst[(size_t)w * a.ntot] = s_list[w * WG + tid];
   }
 }
 
 // ------------------------------------------------------------------ pass B
-template <int T, int LPP, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL>
 __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
@@ -108,7 +156,7 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, L, R, rep)) return;
-  const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
+  const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
     const int g = staged_global<T>(a, L, t);
@@ -120,11 +168,18 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
   }
   __syncthreads();
   const int nin = L.cstart[nint];
-  const int sub = threadIdx.x % LPP;
-  for (int base = 0; base < nin; base += WG / LPP) {
-    const int p = base + threadIdx.x / LPP;
-    const bool act = p < nin;
-    int st = 0;
+  for (int base = 0; base < nin;) {
+    const int lpp = lanes_for(nin - base, a.lpp);
+    const int p = base + threadIdx.x / lpp;
+    const int sub = threadIdx.x & (lpp - 1);
+    base += WG / lpp;
+    int g = -1;
+    if (p < nin) {
+      const int st = find_cell(L.cstart, nint, p);
+      g = L.gstart[st] + (p - L.cstart[st]);
+      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = -1; }
+    }
+    const bool act = g >= 0;
     // raw pair sums (see the epilogue for their meaning)
     Acc<COMP> Sxx, Sxy, Syy, Gxx, Gxy, Gyx, Gyy, Qax, Qay, Qbx, Qby;
     Acc<COMP> Mxx_a, Mxy_a, Myy_a, Mxx_b, Mxy_b, Myy_b, Vsx, Vsy, Wux, Wuy;
@@ -137,79 +192,71 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
     float2 ui = {0.f, 0.f}, qi = {0.f, 0.f};
     float ri = 1.0f;
     if (act) {
-      st = find_cell(L.cstart, nint, p);
-      const int li = st % ni, lj = st / ni;
       const float2 oi = s_off[p];
       ui = s_u[p];
       qi = s_q[p];
       if constexpr (FORM == 1) ri = s_rho[p];
       const float ri2inv = 1.0f / (ri * ri);
-#pragma unroll 1
-      for (int cidx = 0; cidx < 9; ++cidx) {
-          const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
-          const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-          const int j1 = L.cstart[sc + 1];
-          const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-          for (int j = L.cstart[sc] + sub; j < j1; j += LPP) {
-            const float2 oj = s_off[j];
-            float rx, ry, r2;
-            if (!pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) continue;
-            const KW k = quintic(R, r2);
-            const float Vj = s_V[j];
-            const float2 uj = s_u[j], qj = s_q[j];
-            const float c = Vj * k.F;              // V_j W'(r)/r
-            const float cx = c * rx, cy = c * ry;  // V_j grad_i W_ij
-            const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
-            Sxx.add(txx); Sxy.add(txy); Syy.add(tyy);
-            const float dux = uj.x - ui.x, duy = uj.y - ui.y;
-            const float dqa = qj.x - qi.x, dqb = qj.y - qi.y;
-            Gxx.fma(dux, cx); Gxy.fma(dux, cy); Gyx.fma(duy, cx); Gyy.fma(duy, cy);
-            Qax.fma(dqa, cx); Qay.fma(dqa, cy); Qbx.fma(dqb, cx); Qby.fma(dqb, cy);
-            const float e = k.rinv * k.rinv;
-            const float la = -dqa * e, lb = -dqb * e;   // (Q_i - Q_j)/r^2
-            Mxx_a.fma(la, txx); Mxy_a.fma(la, txy); Myy_a.fma(la, tyy);
-            Mxx_b.fma(lb, txx); Mxy_b.fma(lb, txy); Myy_b.fma(lb, tyy);
-            const float sv = -(dux * rx + duy * ry) * e;  // (u_i - u_j).r_ij / r^2
-            if constexpr (FORM == 0) {
-              Vsx.fma(sv, cx); Vsy.fma(sv, cy);
-            } else {
-              const float rj = s_rho[j];
-              const float fx = k.F * rx, fy = k.F * ry;  // grad_i W_ij
-              Kc.add(-(dux * fx + duy * fy));
-              const float svr = sv / rj;
-              V1x.fma(svr, fx); V1y.fma(svr, fy);
-              const float rj2inv = 1.0f / (rj * rj);
-              const float ca = qi.x * ri2inv + qj.x * rj2inv, cb = qi.y * ri2inv + qj.y * rj2inv;
-              A1x.add(ca * fx + cb * fy); A1y.add(cb * fx - ca * fy);
-            }
-            Wux.fma(-dux, k.W); Wuy.fma(-duy, k.W);
-          }
-          Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell();
-          Gxx.end_cell(); Gxy.end_cell(); Gyx.end_cell(); Gyy.end_cell();
-          Qax.end_cell(); Qay.end_cell(); Qbx.end_cell(); Qby.end_cell();
-          Mxx_a.end_cell(); Mxy_a.end_cell(); Myy_a.end_cell();
-          Mxx_b.end_cell(); Mxy_b.end_cell(); Myy_b.end_cell();
-          Vsx.end_cell(); Vsy.end_cell(); Wux.end_cell(); Wuy.end_cell();
-          if constexpr (FORM == 1) { Kc.end_cell(); V1x.end_cell(); V1y.end_cell(); A1x.end_cell(); A1y.end_cell(); }
+      const int cnt = min(a.ncnt[g], KMAX);
+      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+        int j; float rx, ry, r2;
+        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        const KW k = quintic(R, r2);
+        const float Vj = s_V[j];
+        const float2 uj = s_u[j], qj = s_q[j];
+        const float c = Vj * k.F;              // V_j W'(r)/r
+        const float cx = c * rx, cy = c * ry;  // V_j grad_i W_ij
+        const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
+        Sxx.add(txx); Sxy.add(txy); Syy.add(tyy);
+        const float dux = uj.x - ui.x, duy = uj.y - ui.y;
+        const float dqa = qj.x - qi.x, dqb = qj.y - qi.y;
+        Gxx.fma(dux, cx); Gxy.fma(dux, cy); Gyx.fma(duy, cx); Gyy.fma(duy, cy);
+        Qax.fma(dqa, cx); Qay.fma(dqa, cy); Qbx.fma(dqb, cx); Qby.fma(dqb, cy);
+        const float e2 = k.rinv * k.rinv;
+        const float la = -dqa * e2, lb = -dqb * e2;   // (Q_i - Q_j)/r^2
+        Mxx_a.fma(la, txx); Mxy_a.fma(la, txy); Myy_a.fma(la, tyy);
+        Mxx_b.fma(lb, txx); Mxy_b.fma(lb, txy); Myy_b.fma(lb, tyy);
+        const float sv = -(dux * rx + duy * ry) * e2;  // (u_i - u_j).r_ij / r^2
+        if constexpr (FORM == 0) {
+          Vsx.fma(sv, cx); Vsy.fma(sv, cy);
+        } else {
+          const float rj = s_rho[j];
+          const float fx = k.F * rx, fy = k.F * ry;  // grad_i W_ij
+          Kc.add(-(dux * fx + duy * fy));
+          const float svr = sv / rj;
+          V1x.fma(svr, fx); V1y.fma(svr, fy);
+          const float rj2inv = 1.0f / (rj * rj);
+          const float ca = qi.x * ri2inv + qj.x * rj2inv, cb = qi.y * ri2inv + qj.y * rj2inv;
+          A1x.add(ca * fx + cb * fy); A1y.add(cb * fx - ca * fy);
         }
+        Wux.fma(-dux, k.W); Wuy.fma(-duy, k.W);
+      }, [&]() {
+        Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell();
+        Gxx.end_cell(); Gxy.end_cell(); Gyx.end_cell(); Gyy.end_cell();
+        Qax.end_cell(); Qay.end_cell(); Qbx.end_cell(); Qby.end_cell();
+        Mxx_a.end_cell(); Mxy_a.end_cell(); Myy_a.end_cell();
+        Mxx_b.end_cell(); Mxy_b.end_cell(); Myy_b.end_cell();
+        Vsx.end_cell(); Vsy.end_cell(); Wux.end_cell(); Wuy.end_cell();
+        if constexpr (FORM == 1) { Kc.end_cell(); V1x.end_cell(); V1y.end_cell(); A1x.end_cell(); A1y.end_cell(); }
+      });
     }
-    const float sxx = Sxx.template total<LPP>(), sxy = Sxy.template total<LPP>(), syy = Syy.template total<LPP>();
-    const float gxx = Gxx.template total<LPP>(), gxy = Gxy.template total<LPP>();
-    const float gyx = Gyx.template total<LPP>(), gyy = Gyy.template total<LPP>();
-    const float qax = Qax.template total<LPP>(), qay = Qay.template total<LPP>();
-    const float qbx = Qbx.template total<LPP>(), qby = Qby.template total<LPP>();
-    const float mxxa = Mxx_a.template total<LPP>(), mxya = Mxy_a.template total<LPP>(), myya = Myy_a.template total<LPP>();
-    const float mxxb = Mxx_b.template total<LPP>(), mxyb = Mxy_b.template total<LPP>(), myyb = Myy_b.template total<LPP>();
-    const float wux = Wux.template total<LPP>(), wuy = Wuy.template total<LPP>();
+    const float sxx = wave_sum(Sxx.value(), lpp), sxy = wave_sum(Sxy.value(), lpp), syy = wave_sum(Syy.value(), lpp);
+    const float gxx = wave_sum(Gxx.value(), lpp), gxy = wave_sum(Gxy.value(), lpp);
+    const float gyx = wave_sum(Gyx.value(), lpp), gyy = wave_sum(Gyy.value(), lpp);
+    const float qax = wave_sum(Qax.value(), lpp), qay = wave_sum(Qay.value(), lpp);
+    const float qbx = wave_sum(Qbx.value(), lpp), qby = wave_sum(Qby.value(), lpp);
+    const float mxxa = wave_sum(Mxx_a.value(), lpp), mxya = wave_sum(Mxy_a.value(), lpp);
+    const float myya = wave_sum(Myy_a.value(), lpp);
+    const float mxxb = wave_sum(Mxx_b.value(), lpp), mxyb = wave_sum(Mxy_b.value(), lpp);
+    const float myyb = wave_sum(Myy_b.value(), lpp);
+    const float wux = wave_sum(Wux.value(), lpp), wuy = wave_sum(Wuy.value(), lpp);
     float vsx = 0.f, vsy = 0.f, kc = 0.f, v1x = 0.f, v1y = 0.f, a1x = 0.f, a1y = 0.f;
-    if constexpr (FORM == 0) { vsx = Vsx.template total<LPP>(); vsy = Vsy.template total<LPP>(); }
+    if constexpr (FORM == 0) { vsx = wave_sum(Vsx.value(), lpp); vsy = wave_sum(Vsy.value(), lpp); }
     else {
-      kc = Kc.template total<LPP>(); v1x = V1x.template total<LPP>(); v1y = V1y.template total<LPP>();
-      a1x = A1x.template total<LPP>(); a1y = A1y.template total<LPP>();
+      kc = wave_sum(Kc.value(), lpp); v1x = wave_sum(V1x.value(), lpp); v1y = wave_sum(V1y.value(), lpp);
+      a1x = wave_sum(A1x.value(), lpp); a1y = wave_sum(A1y.value(), lpp);
     }
     if (act && sub == 0) {
-      const int g = L.gstart[st] + (p - L.cstart[st]);
-      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
       // alpha = -sum_j V_j W'/r r_ij (x) r_ij, B = alpha^{-1}
       const float axx = -sxx, axy = -sxy, ayy = -syy;
       const float det = axx * ayy - axy * axy;
@@ -238,8 +285,8 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
       // molecular field (2D: the B term vanishes identically)
       const float qa = qi.x, qb = qi.y;
       const float trq2 = 2.0f * (qa * qa + qb * qb);
-      const float cb = R.A + R.C * trq2;
-      const float Ha = -cb * qa + R.K * lapa, Hb = -cb * qb + R.K * lapb;
+      const float cbulk = R.A + R.C * trq2;
+      const float Ha = -cbulk * qa + R.K * lapa, Hb = -cbulk * qb + R.K * lapb;
       // co-rotation projected on symmetric traceless tensors (d = 2)
       const float e12 = 0.5f * (G12 + G21), w12 = 0.5f * (G12 - G21);
       const float QG = qa * (G11 - G22) + 2.0f * qb * e12;
@@ -263,12 +310,24 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
       }
+      if (a.feat) {  // learned-corrector inputs: Q, grad u, H, density, activity
+        const int idl = a.id[g];
+        if (idl >= 0 && idl < R.n) {
+          float* f = a.feat + (size_t)(R.part_base + idl) * 12;
+          f[0] = qa; f[1] = qb; f[2] = -qa;
+          f[3] = G11; f[4] = G12; f[5] = G21; f[6] = G22;
+          f[7] = Ha; f[8] = Hb; f[9] = -Ha;
+          f[10] = drho_n * R.inv_rho0; f[11] = R.zeta;
+        } else {
+          flag(a.flags, ERR_RANGE);
+        }
+      }
     }
   }
 }
 
 // ------------------------------------------------------------------ pass C
-template <int T, int LPP, int COMP>
+template <int T, int COMP>
 __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
@@ -277,7 +336,7 @@ __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, L, R, rep)) return;
-  const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
+  const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
     const int g = staged_global<T>(a, L, t);
@@ -285,40 +344,36 @@ __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
     s_dh[t] = a.dh[g];
   }
   __syncthreads();
-  const float umax = __uint_as_float(a.umax_cur[rep]);
-  const float c0 = R.c0_factor * umax;
+  unsigned umb = 0;
+  for (int k = 0; k < UMAX_SLOTS; ++k) umb = max(umb, a.umax_cur[rep * UMAX_SLOTS + k]);
+  const float c0 = R.c0_factor * __uint_as_float(umb);
   const float pc = R.rho0 * c0 * c0 / R.gamma_eos;
   const int nin = L.cstart[nint];
-  const int sub = threadIdx.x % LPP;
-  for (int base = 0; base < nin; base += WG / LPP) {
-    const int p = base + threadIdx.x / LPP;
-    const bool act = p < nin;
-    int st = 0;
+  for (int base = 0; base < nin;) {
+    const int lpp = lanes_for(nin - base, a.lpp);
+    const int p = base + threadIdx.x / lpp;
+    const int sub = threadIdx.x & (lpp - 1);
+    base += WG / lpp;
+    int g = -1;
+    if (p < nin) {
+      const int st = find_cell(L.cstart, nint, p);
+      g = L.gstart[st] + (p - L.cstart[st]);
+      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = -1; }
+    }
+    const bool act = g >= 0;
     Acc<COMP> sd;
     sd.init();
     if (act) {
-      st = find_cell(L.cstart, nint, p);
-      const int li = st % ni, lj = st / ni;
       const float2 oi = s_off[p];
-#pragma unroll 1
-      for (int cidx = 0; cidx < 9; ++cidx) {
-          const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
-          const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-          const int j1 = L.cstart[sc + 1];
-          const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-          for (int j = L.cstart[sc] + sub; j < j1; j += LPP) {
-            const float2 oj = s_off[j];
-            float rx, ry, r2;
-            if (pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2))
-              sd.fma(s_dh[j], quintic_W(R, r2));
-          }
-          sd.end_cell();
-        }
+      const int cnt = min(a.ncnt[g], KMAX);
+      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+        int j; float rx, ry, r2;
+        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        sd.fma(s_dh[j], quintic_W(R, r2));
+      }, [&]() { sd.end_cell(); });
     }
-    const float tot = sd.template total<LPP>();
+    const float tot = wave_sum(sd.value(), lpp);
     if (act && sub == 0) {
-      const int g = L.gstart[st] + (p - L.cstart[st]);
-      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
       const float Vi = a.V[g];
       const float dhi = s_dh[p];
       // Shepard filter with the self term, written for rho - rho0
@@ -338,7 +393,7 @@ __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
 }
 
 // ------------------------------------------------------------------ pass D
-template <int T, int LPP, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL>
 __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
@@ -346,10 +401,11 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
   __shared__ float s_V[MP];
   __shared__ float s_P[MP];
   __shared__ float2 s_pi[EL == 1 ? MP : 1];
+  __shared__ float s_wmax[WG / 64];
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, L, R, rep)) return;
-  const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
+  const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
     const int g = staged_global<T>(a, L, t);
@@ -360,65 +416,54 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
   }
   __syncthreads();
   const int nin = L.cstart[nint];
-  const int sub = threadIdx.x % LPP;
-  float umax_w = 0.0f;
+  float umax_l = 0.0f;
   bool rebin = false, bad = false;
-  for (int base = 0; base < nin; base += WG / LPP) {
-    const int p = base + threadIdx.x / LPP;
-    const bool act = p < nin;
-    int st = 0;
-    Acc<COMP> Px, Py, Rx3, Ry3, Rs, Exx, Exy, Eyx, Eyy;
-    Px.init(); Py.init(); Rx3.init(); Ry3.init(); Rs.init();
-    Exx.init(); Exy.init(); Eyx.init(); Eyy.init();
-    int cnt = 0;
+  for (int base = 0; base < nin;) {
+    const int lpp = lanes_for(nin - base, a.lpp);
+    const int p = base + threadIdx.x / lpp;
+    const int sub = threadIdx.x & (lpp - 1);
+    base += WG / lpp;
+    int g = -1;
+    if (p < nin) {
+      const int st = find_cell(L.cstart, nint, p);
+      g = L.gstart[st] + (p - L.cstart[st]);
+      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = -1; }
+    }
+    const bool act = g >= 0;
+    Acc<COMP> Px, Py, Exx, Exy, Eyx, Eyy;
+    Px.init(); Py.init(); Exx.init(); Exy.init(); Eyx.init(); Eyy.init();
     float2 oi = {0.f, 0.f};
     if (act) {
-      st = find_cell(L.cstart, nint, p);
-      const int li = st % ni, lj = st / ni;
       oi = s_off[p];
       const float Pi = s_P[p];
       float2 pii = {0.f, 0.f};
       if constexpr (EL == 1) pii = s_pi[p];
-#pragma unroll 1
-      for (int cidx = 0; cidx < 9; ++cidx) {
-          const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
-          const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-          const int j1 = L.cstart[sc + 1];
-          const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-          for (int j = L.cstart[sc] + sub; j < j1; j += LPP) {
-            const float2 oj = s_off[j];
-            float rx, ry, r2;
-            if (!pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) continue;
-            const KW k = quintic(R, r2);
-            const float c = (FORM == 0) ? s_V[j] * k.F : k.F;
-            const float f = (Pi + s_P[j]) * c;
-            Px.fma(f, rx); Py.fma(f, ry);
-            if constexpr (EL == 1) {
-              const float2 pj = s_pi[j];
-              const float cx = c * rx, cy = c * ry;
-              const float dpa = pj.x - pii.x, dpb = pj.y - pii.y;
-              Exx.fma(dpa, cx); Exy.fma(dpa, cy); Eyx.fma(dpb, cx); Eyy.fma(dpb, cy);
-            }
-            const float r3 = k.rinv * k.rinv * k.rinv;
-            Rx3.fma(rx, r3); Ry3.fma(ry, r3); Rs.add(k.r);
-            ++cnt;
-          }
-          Px.end_cell(); Py.end_cell(); Rx3.end_cell(); Ry3.end_cell(); Rs.end_cell();
-          if constexpr (EL == 1) { Exx.end_cell(); Exy.end_cell(); Eyx.end_cell(); Eyy.end_cell(); }
+      const int cnt = min(a.ncnt[g], KMAX);
+      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+        int j; float rx, ry, r2;
+        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        const KW k = quintic(R, r2);
+        const float c = (FORM == 0) ? s_V[j] * k.F : k.F;
+        const float f = (Pi + s_P[j]) * c;
+        Px.fma(f, rx); Py.fma(f, ry);
+        if constexpr (EL == 1) {
+          const float2 pj = s_pi[j];
+          const float cx = c * rx, cy = c * ry;
+          const float dpa = pj.x - pii.x, dpb = pj.y - pii.y;
+          Exx.fma(dpa, cx); Exy.fma(dpa, cy); Eyx.fma(dpb, cx); Eyy.fma(dpb, cy);
         }
+      }, [&]() {
+        Px.end_cell(); Py.end_cell();
+        if constexpr (EL == 1) { Exx.end_cell(); Exy.end_cell(); Eyx.end_cell(); Eyy.end_cell(); }
+      });
     }
-    const float prx = Px.template total<LPP>(), pry = Py.template total<LPP>();
-    const float srx = Rx3.template total<LPP>(), sry = Ry3.template total<LPP>(), sr = Rs.template total<LPP>();
+    const float prx = wave_sum(Px.value(), lpp), pry = wave_sum(Py.value(), lpp);
     float exx = 0.f, exy = 0.f, eyx = 0.f, eyy = 0.f;
     if constexpr (EL == 1) {
-      exx = Exx.template total<LPP>(); exy = Exy.template total<LPP>();
-      eyx = Eyx.template total<LPP>(); eyy = Eyy.template total<LPP>();
+      exx = wave_sum(Exx.value(), lpp); exy = wave_sum(Exy.value(), lpp);
+      eyx = wave_sum(Eyx.value(), lpp); eyy = wave_sum(Eyy.value(), lpp);
     }
-#pragma unroll
-    for (int o = 1; o < LPP; o <<= 1) cnt += __shfl_xor(cnt, o, 64);
     if (act && sub == 0) {
-      const int g = L.gstart[st] + (p - L.cstart[st]);
-      if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
       const float4 bk = a.bk[g];
       const float drh = a.drhat[g];
       const float rh = R.rho0 + drh;
@@ -441,10 +486,11 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
       const float hdt = 0.5f * R.dt;
       const float u1x = uh.x + hdt * ax, u1y = uh.y + hdt * ay;   // u^{n+1}
       float drx = 0.f, dry = 0.f;
-      if (R.apd && cnt > 0) {
-        const float r0 = sr / (float)cnt;
+      const float4 ag = a.apdg[g];  // sum rx/r^3, sum ry/r^3, sum r, count
+      if (R.apd && ag.w > 0.0f) {
+        const float r0 = ag.z / ag.w;
         const float f = r0 * r0 * a.uv[g] * R.dt;
-        drx = f * srx; dry = f * sry;
+        drx = f * ag.x; dry = f * ag.y;
       }
       const float unx = u1x + hdt * ax, uny = u1y + hdt * ay;      // u^{n+3/2}
       const float dispx = hdt * u1x + drx + hdt * unx;
@@ -463,24 +509,111 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
         l2 = lo.y + e;
         nh.y = s + l2; nl.y = l2 - (nh.y - s);
       }
+      const float dn = drh + hdt * bk.w;
       a.off_nxt[g] = nh;
       a.offlo[g] = nl;
       a.u[g] = make_float2(unx, uny);
       a.acc[g] = make_float2(ax, ay);
-      a.drho[g] = drh + hdt * bk.w;
-      umax_w = fmaxf(umax_w, sqrtf(unx * unx + uny * uny));
+      a.drho[g] = dn;
+      umax_l = fmaxf(umax_l, sqrtf(unx * unx + uny * uny));
       if (nh.x < -R.skin_half || nh.x > R.cs + R.skin_half || nh.y < -R.skin_half || nh.y > R.cs + R.skin_half)
         rebin = true;
-      if (!(isfinite(unx) && isfinite(uny) && isfinite(nh.x) && isfinite(nh.y) && isfinite(a.drho[g])))
-        bad = true;
+      if (!(isfinite(unx) && isfinite(uny) && isfinite(nh.x) && isfinite(nh.y) && isfinite(dn))) bad = true;
     }
   }
-  // one atomic per wave for the max speed; NaN speeds are reported as errors
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) umax_w = fmaxf(umax_w, __shfl_xor(umax_w, o, 64));
-  if ((threadIdx.x & 63) == 0 && umax_w > 0.0f) atomicMax(&a.umax_nxt[rep], __float_as_uint(umax_w));
+  // max speed: wave shuffles, LDS across waves, one atomic per workgroup into
+  // one of UMAX_SLOTS slots of the replica (pass C takes the max of the slots)
+  for (int o = 1; o < 64; o <<= 1) umax_l = fmaxf(umax_l, __shfl_xor(umax_l, o, 64));
+  if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = umax_l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = 0.0f;
+    for (int w = 0; w < WG / 64; ++w) m = fmaxf(m, s_wmax[w]);
+    if (m > 0.0f) atomicMax(&a.umax_nxt[rep * UMAX_SLOTS + (blockIdx.x & (UMAX_SLOTS - 1))], __float_as_uint(m));
+  }
   if (rebin) atomicOr(&a.flags[1], 1u);
   if (bad) flag(a.flags, ERR_NUMERIC);
+}
+
+// ------------------------------------------------------- free energy (FP64)
+// Per-particle contributions to the free energy of Eq. freeenergy at the
+// integer time level, with the elastic part written through the discrete
+// Laplacian (F) and through squared corrected gradients (F_grad):
+//   F_i    = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 - K/2 Q:lapQ]
+//   F_grad = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 + K/2 sum_abc (d_c Q_ab)^2]
+// (trQ^3 = 0 in 2D). Runs after pass A on the integer-level offsets.
+template <int T>
+__global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe) {
+  __shared__ TileLDS<T> L;
+  constexpr int MP = TileCfg<T>::MAXP;
+  __shared__ float2 s_off[MP];
+  __shared__ float2 s_q[MP];
+  __shared__ float s_V[MP];
+  RepDev R;
+  int rep;
+  if (!tile_begin<T>(a, L, R, rep)) return;
+  const int nint = L.hdr[2], nreg = L.hdr[3];
+  const int S = L.cstart[nreg];
+  for (int t = threadIdx.x; t < S; t += WG) {
+    const int g = staged_global<T>(a, L, t);
+    s_off[t] = a.off_cur[g];
+    s_q[t] = a.q_cur[g];
+    s_V[t] = a.V[g];
+  }
+  __syncthreads();
+  const int nin = L.cstart[nint];
+  for (int p = threadIdx.x; p < nin; p += WG) {
+    const int st = find_cell(L.cstart, nint, p);
+    const int g = L.gstart[st] + (p - L.cstart[st]);
+    if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
+    const float2 oi = s_off[p], qi = s_q[p];
+    Acc<1> Sxx, Sxy, Syy, Qax, Qay, Qbx, Qby, Mxxa, Mxya, Myya, Mxxb, Mxyb, Myyb;
+    Sxx.init(); Sxy.init(); Syy.init(); Qax.init(); Qay.init(); Qbx.init(); Qby.init();
+    Mxxa.init(); Mxya.init(); Myya.init(); Mxxb.init(); Mxyb.init(); Myyb.init();
+    each_listed(a.nl, a.ntot, g, min(a.ncnt[g], KMAX), 1, 0, [&](uint32_t e) {
+      int j; float rx, ry, r2;
+      listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+      const KW k = quintic(R, r2);
+      const float c = s_V[j] * k.F, cx = c * rx, cy = c * ry;
+      const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
+      Sxx.add(txx); Sxy.add(txy); Syy.add(tyy);
+      const float2 qj = s_q[j];
+      const float dqa = qj.x - qi.x, dqb = qj.y - qi.y, e2 = k.rinv * k.rinv;
+      Qax.fma(dqa, cx); Qay.fma(dqa, cy); Qbx.fma(dqb, cx); Qby.fma(dqb, cy);
+      const float la = -dqa * e2, lb = -dqb * e2;
+      Mxxa.fma(la, txx); Mxya.fma(la, txy); Myya.fma(la, tyy);
+      Mxxb.fma(lb, txx); Mxyb.fma(lb, txy); Myyb.fma(lb, tyy);
+    }, [&]() {
+      Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell(); Qax.end_cell(); Qay.end_cell(); Qbx.end_cell();
+      Qby.end_cell(); Mxxa.end_cell(); Mxya.end_cell(); Myya.end_cell(); Mxxb.end_cell(); Mxyb.end_cell();
+      Myyb.end_cell();
+    });
+    const float axx = -Sxx.value(), axy = -Sxy.value(), ayy = -Syy.value();
+    const float det = axx * ayy - axy * axy;
+    float Bxx = 1.f, Bxy = 0.f, Byy = 1.f;
+    if (det > 1e-12f * (axx * axx + 2.0f * axy * axy + ayy * ayy) && isfinite(det)) {
+      const float id = 1.0f / det;
+      Bxx = ayy * id; Bxy = -axy * id; Byy = axx * id;
+    }
+    const double dax = Qax.value() * Bxx + Qay.value() * Bxy, day = Qax.value() * Bxy + Qay.value() * Byy;
+    const double dbx = Qbx.value() * Bxx + Qby.value() * Bxy, dby = Qbx.value() * Bxy + Qby.value() * Byy;
+    const double lapa = 2.0 * (Bxx * Mxxa.value() + 2.0f * Bxy * Mxya.value() + Byy * Myya.value());
+    const double lapb = 2.0 * (Bxx * Mxxb.value() + 2.0f * Bxy * Mxyb.value() + Byy * Myyb.value());
+    const double qa = qi.x, qb = qi.y, t2 = 2.0 * (qa * qa + qb * qb);
+    const double bulk = 0.5 * (double)R.A * t2 + 0.25 * (double)R.C * t2 * t2;
+    const double Vi = s_V[p];
+    // Q:lapQ and sum of squared gradients over the four components of Q
+    const double qlq = 2.0 * (qa * lapa + qb * lapb);
+    const double g2 = 2.0 * (dax * dax + day * day + dbx * dbx + dby * dby);
+    fe[g] = Vi * (bulk - 0.5 * (double)R.K * qlq);
+    fe[(size_t)a.ntot + g] = Vi * (bulk + 0.5 * (double)R.K * g2);
+  }
+}
+
+void launch_free_energy(int T, const StepArgs& a, double* fe, hipStream_t s) {
+  const dim3 grid(a.nwork), block(WG);
+  if (T == 8) hipLaunchKernelGGL((k_free_energy<8>), grid, block, 0, s, a, fe);
+  else hipLaunchKernelGGL((k_free_energy<4>), grid, block, 0, s, a, fe);
 }
 
 // ---------------------------------------------------------- neighbour export
@@ -514,9 +647,8 @@ __global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* s
     if (idi < 0 || idi >= R.n) { flag(a.flags, ERR_RANGE); continue; }
     int c = 0;
     int64_t base = (mode == 1) ? row_ptr[idi] : 0;
-#pragma unroll 1
-    for (int cidx = 0; cidx < 9; ++cidx) {
-        const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
         const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
         const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
         for (int j = L.cstart[sc]; j < L.cstart[sc + 1]; ++j) {
@@ -536,38 +668,40 @@ __global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* s
 }
 
 // ------------------------------------------------------------- dispatch
-template <int T, int LPP, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL>
 static void launch4(int pass, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.nwork), block(WG);
   switch (pass) {
-    case 1: hipLaunchKernelGGL((k_pass_a<T, LPP, COMP>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass_b<T, LPP, COMP, FORM, EL>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pass_c<T, LPP, COMP>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pass_d<T, LPP, COMP, FORM, EL>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass_a<T, COMP>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pass_c<T, COMP>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL>), grid, block, 0, s, a); break;
   }
 }
 
-// Supported combinations: the default physics (form 0, reduced stress) for
-// tiles of 4 or 8 cells and 1, 2 or 4 lanes per particle with per-cell
-// compensation; every compensation mode at T = 4, LPP = 1; the conservative
-// form and the elastic lambda terms at T = 4, LPP = 1.
-bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
-  if (c.FORM == 0 && c.EL == 0) {
-    if (c.COMP == 1) {
-      if (c.T == 4 && c.LPP == 1) { launch4<4, 1, 1, 0, 0>(pass, a, s); return true; }
-      if (c.T == 4 && c.LPP == 2) { launch4<4, 2, 1, 0, 0>(pass, a, s); return true; }
-      if (c.T == 4 && c.LPP == 4) { launch4<4, 4, 1, 0, 0>(pass, a, s); return true; }
-      if (c.T == 8 && c.LPP == 1) { launch4<8, 1, 1, 0, 0>(pass, a, s); return true; }
-      if (c.T == 8 && c.LPP == 2) { launch4<8, 2, 1, 0, 0>(pass, a, s); return true; }
-      if (c.T == 8 && c.LPP == 4) { launch4<8, 4, 1, 0, 0>(pass, a, s); return true; }
-    }
-    if (c.T == 4 && c.LPP == 1 && c.COMP == 0) { launch4<4, 1, 0, 0, 0>(pass, a, s); return true; }
-    if (c.T == 4 && c.LPP == 1 && c.COMP == 2) { launch4<4, 1, 2, 0, 0>(pass, a, s); return true; }
-    return false;
+template <int T, int COMP>
+static bool launch_phys(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
+  if (c.FORM == 0 && c.EL == 0) { launch4<T, COMP, 0, 0>(pass, a, s); return true; }
+  if (c.FORM == 1 && c.EL == 0) { launch4<T, COMP, 1, 0>(pass, a, s); return true; }
+  if (c.FORM == 0 && c.EL == 1) { launch4<T, COMP, 0, 1>(pass, a, s); return true; }
+  return false;
+}
+
+template <int T>
+static bool launch_comp(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
+  switch (c.COMP) {
+    case 0: return launch_phys<T, 0>(pass, c, a, s);
+    case 1: return launch_phys<T, 1>(pass, c, a, s);
+    case 2: return launch_phys<T, 2>(pass, c, a, s);
   }
-  if (c.T != 4 || c.LPP != 1 || c.COMP != 1) return false;
-  if (c.FORM == 1 && c.EL == 0) { launch4<4, 1, 1, 1, 0>(pass, a, s); return true; }
-  if (c.FORM == 0 && c.EL == 1) { launch4<4, 1, 1, 0, 1>(pass, a, s); return true; }
+  return false;
+}
+
+// Tiles of 4 or 8 cells; lanes per particle (1, 2, 4) is a runtime argument.
+bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
+  if (c.LPP != 1 && c.LPP != 2 && c.LPP != 4) return false;
+  if (c.T == 4) return launch_comp<4>(pass, c, a, s);
+  if (c.T == 8) return launch_comp<8>(pass, c, a, s);
   return false;
 }
 

@@ -64,7 +64,7 @@ __global__ void k_ingest(SortArgs s, int r, const double* __restrict__ in, int n
     s.t_acc[k] = make_float2((float)ax[i], (float)ay[i]);
     s.t_id[k] = i;
     atomicAdd(&s.count[key], 1);
-    atomicMax(&umax[r], __float_as_uint(sqrtf(uf.x * uf.x + uf.y * uf.y)));
+    atomicMax(&umax[r * UMAX_SLOTS + (i & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(uf.x * uf.x + uf.y * uf.y)));
   }
 }
 
@@ -204,7 +204,7 @@ __global__ void k_gather(SortArgs s, int k0, int n, int c0, int nc) {
 __global__ void k_step_begin(unsigned* flags, unsigned* umax_nxt, int R) {
   const int t = threadIdx.x;
   if (t == 0) flags[1] = 0u;
-  for (int r = t; r < R; r += blockDim.x) umax_nxt[r] = 0u;
+  for (int r = t; r < R * UMAX_SLOTS; r += blockDim.x) umax_nxt[r] = 0u;
 }
 
 // Sorted state of replica r -> FP64 arrays in id order at the integer time
@@ -240,13 +240,14 @@ __global__ void k_export(SortArgs s, int r, double* out, int n) {
 
 // FP64 reductions of replica r at the integer time level (fixed grid, fixed
 // tree: the result does not depend on scheduling). Stage 1: one partial per
-// block in red[64 + 8*b + k]; stage 2 sums them in order into red[0..7]:
-// sum ux, sum uy, sum |u|^2 / 2, max |u|, max |Q|_F.
+// block in red[64 + 8*b + k]; stage 2 sums them in order into red[0..6]:
+// sum ux, sum uy, sum |u|^2 / 2, max |u|, max |Q|_F, sum F_i, sum F_grad_i
+// (fe = per-particle free-energy terms, ntot apart; may be NULL).
 constexpr int RED_BLOCKS = 256;
-__global__ __launch_bounds__(256) void k_reduce1(SortArgs s, int r, int n, double* red) {
+__global__ __launch_bounds__(256) void k_reduce1(SortArgs s, int r, int n, const double* fe, double* red) {
   const RepDev R = s.reps[r];
-  __shared__ double sh[5][256];
-  double a0 = 0, a1 = 0, a2 = 0, m0 = 0, m1 = 0;
+  __shared__ double sh[7][256];
+  double a0 = 0, a1 = 0, a2 = 0, m0 = 0, m1 = 0, f0 = 0, f1 = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int k = R.part_base + i;
     const float2 uh = s.u[k], ac = s.acc[k], q = s.q[k];
@@ -256,27 +257,41 @@ __global__ __launch_bounds__(256) void k_reduce1(SortArgs s, int r, int n, doubl
     a0 += ux; a1 += uy; a2 += 0.5 * u2;
     m0 = fmax(m0, sqrt(u2));
     m1 = fmax(m1, sqrt(2.0 * ((double)q.x * q.x + (double)q.y * q.y)));
+    if (fe) { f0 += fe[k]; f1 += fe[(size_t)s.ntot + k]; }
   }
   const int t = threadIdx.x;
-  sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = m0; sh[4][t] = m1;
+  sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = m0; sh[4][t] = m1; sh[5][t] = f0; sh[6][t] = f1;
   __syncthreads();
   for (int d = 128; d > 0; d >>= 1) {
     if (t < d) {
       sh[0][t] += sh[0][t + d]; sh[1][t] += sh[1][t + d]; sh[2][t] += sh[2][t + d];
       sh[3][t] = fmax(sh[3][t], sh[3][t + d]); sh[4][t] = fmax(sh[4][t], sh[4][t + d]);
+      sh[5][t] += sh[5][t + d]; sh[6][t] += sh[6][t + d];
     }
     __syncthreads();
   }
-  if (t < 5) red[64 + 8 * blockIdx.x + t] = sh[t][0];
+  if (t < 7) red[64 + 8 * blockIdx.x + t] = sh[t][0];
 }
 __global__ void k_reduce2(double* red) {
   if (threadIdx.x != 0) return;
-  double v[5] = {0, 0, 0, 0, 0};
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int b = 0; b < RED_BLOCKS; ++b) {
     for (int k = 0; k < 3; ++k) v[k] += red[64 + 8 * b + k];
     for (int k = 3; k < 5; ++k) v[k] = fmax(v[k], red[64 + 8 * b + k]);
+    for (int k = 5; k < 7; ++k) v[k] += red[64 + 8 * b + k];
   }
-  for (int k = 0; k < 5; ++k) red[k] = v[k];
+  for (int k = 0; k < 7; ++k) red[k] = v[k];
+}
+
+// Integer-level offsets r^n = r^{n+1/2} - u^{n+1/2} dt/2 relative to the binned
+// cells (FP32), for diagnostics that need the pair geometry at r^n.
+__global__ void k_int_offsets(SortArgs s, float2* out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of_particle(s.reps, s.R, k);
+    const float hdt = 0.5f * s.reps[r].dt;
+    const float2 o = s.off[k], lo = s.offlo[k], u = s.u[k];
+    out[k] = make_float2(o.x + (lo.x - hdt * u.x), o.y + (lo.y - hdt * u.y));
+  }
 }
 
 // -------------------------------------------------------------- launchers
@@ -297,8 +312,11 @@ void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base
 void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st) {
   hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, st, flags, umax_nxt, R);
 }
-void launch_reduce(const SortArgs& s, int r, int n, double* red, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, st, s, r, n, red);
+void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_int_offsets, dim3(grid_for(s.ntot)), dim3(256), 0, st, s, out);
+}
+void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, st, s, r, n, fe, red);
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, st, red);
 }
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st) {

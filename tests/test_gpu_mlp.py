@@ -1,0 +1,172 @@
+"""The learned corrector on the GPU: BF16-MFMA forward and backward kernels
+against the FP64 reference network on the same (BF16-rounded) weights and
+inputs, training, sample generation from the solver, and the learned macro
+step with its fallback."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+import workloads as wl
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import field_errors, gpu_run, random_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+IDENT = np.concatenate([np.zeros(12), np.ones(12), np.zeros(5), np.ones(5)]).astype(np.float32)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_08919_amd as P
+    P.lib()
+    yield
+
+
+def cosine(a, b):
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def setup(n, seed):
+    import torch
+    import paper_2108_08919_amd as P
+    rng = np.random.default_rng(seed)
+    params = [p + 0.05 * rng.normal(size=p.shape) for p in ref.init(seed)]
+    w32 = ref.flatten(params).astype(np.float32)
+    X = rng.normal(size=(n, 12)).astype(np.float32)
+    T = rng.normal(size=(n, 5)).astype(np.float32)
+    m = P.Mlp()
+    m.set_weights(w32)
+    m.set_norm(IDENT)
+    Xt = torch.from_numpy(X).cuda()
+    Tt = torch.from_numpy(T).cuda()
+    # reference on the values the GPU sees: BF16 weights and inputs
+    pb = [ref.to_bf16(p) for p in ref.unflatten(w32.astype(np.float64))]
+    for k in (1, 3, 5):                  # biases stay FP32 on the GPU
+        pb[k] = ref.unflatten(w32.astype(np.float64))[k]
+    return m, Xt, Tt, pb, ref.to_bf16(X.astype(np.float64)), T.astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [32, 1000, 4133])
+def test_forward_matches_reference(n):
+    m, Xt, Tt, pb, Xb, T = setup(n, 1)
+    Y = m.forward(Xt).cpu().numpy().astype(np.float64)
+    y_ref, _ = ref.forward(pb, Xb)
+    rel = np.linalg.norm(Y - y_ref) / np.linalg.norm(y_ref)
+    print("forward rel", rel, "cos", cosine(Y.ravel(), y_ref.ravel()), flush=True)
+    assert cosine(Y.ravel(), y_ref.ravel()) >= 0.999
+    assert rel <= 2e-2
+    m.close()
+
+
+@pytest.mark.parametrize("n", [64, 2050])
+def test_gradient_matches_reference(n):
+    m, Xt, Tt, pb, Xb, T = setup(n, 2)
+    g, loss = m.grad(Xt, Tt)
+    g_ref = ref.flatten(ref.grad(pb, Xb, T))
+    l_ref = ref.loss(pb, Xb, T)
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print("grad rel", rel, "cos", cosine(g, g_ref), "loss", loss, l_ref, flush=True)
+    assert cosine(g.astype(np.float64), g_ref) >= 0.999
+    assert rel <= 2e-2
+    assert loss == pytest.approx(l_ref, rel=2e-2)
+    # every block of the flat vector is non-trivially matched
+    off = 0
+    for a, b in [(12, 64), (64, 64), (64, 5)]:
+        for size in (a * b, b):
+            blk = slice(off, off + size)
+            assert cosine(g[blk].astype(np.float64), g_ref[blk]) >= 0.99
+            off += size
+    m.close()
+
+
+def test_training_reduces_loss():
+    import torch
+    import paper_2108_08919_amd as P
+    rng = np.random.default_rng(3)
+    n = 8192
+    X = rng.normal(size=(n, 12)).astype(np.float32)
+    Wt = rng.normal(size=(12, 5)) * 0.4
+    T = (np.tanh(X @ Wt) * 3.0 + 1.0).astype(np.float32)
+    m = P.Mlp()
+    m.set_weights(ref.flatten(ref.init(0)).astype(np.float32))
+    Xt, Tt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    m.fit_norm(Xt, Tt)
+    nm = m.get_norm()
+    assert np.allclose(nm[:12], X.mean(0), atol=1e-4) and np.allclose(nm[12:24], X.std(0), rtol=1e-4)
+    _, l0 = m.grad(Xt, Tt)
+    m.train(Xt, Tt, epochs=30, batch=512, lr=3e-3)
+    _, l1 = m.grad(Xt, Tt)
+    print("loss", l0, "->", l1, flush=True)
+    assert l1 < 0.1 * l0
+    Y = m.forward(Xt).cpu().numpy()
+    assert np.linalg.norm(Y - T) / np.linalg.norm(T - T.mean(0)) < 0.3
+    m.close()
+
+
+def test_samples_leave_state_unchanged():
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    s0 = random_state(L, 21, amp_u=3e-3)
+    g0, sim = gpu_run(p, s0, 3)
+    X, T = sim.samples(4)
+    g1 = sim.get_state(0)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+    X, T = X.cpu().numpy(), T.cpu().numpy()
+    assert X.shape == (L * L, 12) and T.shape == (L * L, 5)
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(T))
+    assert np.allclose(X[:, 0], g0["qxx"], atol=1e-6) and np.allclose(X[:, 2], -g0["qxx"], atol=1e-6)
+    assert np.all(X[:, 11] == np.float32(p.zeta))
+    assert np.allclose(T[:, 2], -T[:, 0], atol=1e-7)
+    # targets are the small difference between fine and coarse stepping
+    assert np.abs(T[:, :2]).max() < 1e-2 * np.abs(X[:, :2]).max()
+    sim.close()
+
+
+def test_learned_step_zero_network_is_coarse_stepping():
+    import paper_2108_08919_amd as P
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    s0 = random_state(L, 22, amp_u=3e-3)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    m = P.Mlp()
+    m.set_weights(np.zeros(m.nparams, dtype=np.float32))
+    m.set_norm(IDENT)
+    nfb, mx = sim.step_learned(m, 5, 4, 1.0)
+    sim.check()
+    g = sim.get_state(0)
+    c, sc = gpu_run(p.replace(dt=4 * p.dt), s0, 5)
+    e = field_errors(g, c, s0, L)
+    print(e, flush=True)
+    assert nfb == 0 and mx == 0.0
+    assert e["u"] < 1e-5 and e["Q"] < 1e-6 and e["rho"] < 1e-9 and e["pos_abs_max"] < 1e-7
+    sim.close(); sc.close(); m.close()
+
+
+def test_learned_step_fallback_is_fine_stepping():
+    import paper_2108_08919_amd as P
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    s0 = random_state(L, 23, amp_u=3e-3)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    m = P.Mlp()
+    m.set_weights(ref.flatten(ref.init(5)).astype(np.float32))
+    m.set_norm(IDENT)
+    nfb, mx = sim.step_learned(m, 3, 4, 1e-30)
+    sim.check()
+    assert nfb == 3
+    g = sim.get_state(0)
+    f, sf = gpu_run(p, s0, 12)
+    e = field_errors(g, f, s0, L)
+    print(e, flush=True)
+    assert e["u"] < 1e-5 and e["Q"] < 1e-6 and e["pos_abs_max"] < 1e-7
+    sim.close(); sf.close(); m.close()
