@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--comp", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-check", action="store_true", help="also time the hipGraph replay path")
+    ap.add_argument("--workload", choices=("box", "ensemble"), default="box",
+                    help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -57,6 +59,8 @@ def main():
     import paper_2108_08919_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "ensemble":
+        return ensemble(args)
     cfg = wl.config("C4")
     p = cfg["params"]
     if args.side != 2048:
@@ -147,6 +151,43 @@ def main():
         "graph_value": graph_value,
         "cpu_baseline": cpu,
     }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+def ensemble(args):
+    """32 replicas, sides drawn from U{128..384} (seeded), zeta x K sweep x 2
+    seeds, advanced together: one launch per pass over the tiles of all
+    replicas, autotuned launch shape, steps replayed from a captured graph."""
+    import torch
+    import workloads as wl
+    import paper_2108_08919_amd as P
+    reps = wl.ensemble(0)
+    params = [r["params"] for r in reps]
+    ns = [r["n_side"] ** 2 for r in reps]
+    sim = P.Sim(params, ns)
+    for i, r in enumerate(reps):
+        sim.set_state(i, wl.state_for(r))
+    sim.step(2)
+    tile, lpp, _ = sim.autotune(3)
+    sim.set_option(P.NEM_OPT_GRAPH, 10)
+    sim.step(args.warmup)
+    sim.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    rc = sim.sync()
+    t1 = time.perf_counter()
+    if rc != 0:
+        raise SystemExit(f"device error {rc}: {P.strerror(rc)}")
+    N = sum(ns)
+    value = N * args.steps / (t1 - t0)
+    out = {"metric": "SPH particle-steps/s, batched ensemble", "value": value, "unit": "particle-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(reps)} replicas, sides U{{128..384}}, {N} particles, zeta x K sweep",
+                      "particles": N, "tile": tile, "lanes_per_particle": lpp, "graph_steps": 10},
+           "hbm_frac_algorithmic": value * sum(BYTES_PER_PARTICLE.values()) / HBM_PEAK}
     sim.close()
     print(json.dumps(out), flush=True)
 

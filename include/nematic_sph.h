@@ -160,15 +160,25 @@ int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_mi
  *   NEM_OPT_LPP        lanes per particle in the pair loops (1, 2 or 4)
  *   NEM_OPT_COMP       pair-sum compensation: 0 none, 1 per stencil cell, 2 per pair
  *   NEM_OPT_TIMING     1: record HIP events around every pass launch
- *   NEM_OPT_GRAPH      1: capture one step per buffer parity into a hipGraph
- *                      and replay it (ignored while timing is on)
+ *   NEM_OPT_GRAPH      k > 0: capture k consecutive steps per buffer parity into
+ *                      a hipGraph and replay it (steps left over run eagerly;
+ *                      ignored while timing is on); 0: eager launches
+ *   NEM_OPT_PERSIST    g > 0: pair passes run as g workgroups looping over the
+ *                      tile work list of all replicas; 0: one workgroup per tile
  * Changing an option drops captured graphs. */
 #define NEM_OPT_TILE 1
 #define NEM_OPT_LPP 2
 #define NEM_OPT_COMP 3
 #define NEM_OPT_TIMING 4
 #define NEM_OPT_GRAPH 5
+#define NEM_OPT_PERSIST 6
 int nem_set_option(nem_sim* s, int32_t key, int64_t value);
+
+/* Autotuner: times `steps` steps of every supported (tile side, lanes per
+ * particle) pair on the current state of all replicas (restoring the state
+ * after each trial), keeps the fastest and returns it (*tile, *lpp, and the
+ * best ms per step; each may be NULL). Allocates a state snapshot (hipMalloc). */
+int nem_autotune(nem_sim* s, int32_t steps, int32_t* tile, int32_t* lpp, double* ms_per_step);
 
 /* Accumulated kernel times (ms, from HIP events recorded on the library's
  * stream around each launch group) and launch counts since the last reset,

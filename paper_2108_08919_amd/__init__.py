@@ -34,6 +34,7 @@ NEM_OPT_LPP = 2
 NEM_OPT_COMP = 3
 NEM_OPT_TIMING = 4
 NEM_OPT_GRAPH = 5
+NEM_OPT_PERSIST = 6
 NEM_NPASS = 5
 PASS_NAMES = ("rebin", "pass_a_volume", "pass_b_rates", "pass_c_eos", "pass_d_update")
 
@@ -42,7 +43,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_set_option", "nem_pass_times", "nem_strerror", "nem_last_error", "nem_destroy",
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
-            "nem_mlp_destroy", "nem_samples", "nem_step_learned")
+            "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune")
 
 
 class NemParams(C.Structure):
@@ -129,6 +130,8 @@ def lib(path: Optional[str] = None):
     L.nem_samples.argtypes = [vp, C.c_int32, vp, vp]
     L.nem_step_learned.restype = C.c_int
     L.nem_step_learned.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_double, C.POINTER(C.c_int64), dp]
+    L.nem_autotune.restype = C.c_int
+    L.nem_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
     L.nem_strerror.restype = C.c_char_p
     L.nem_strerror.argtypes = [C.c_int]
     L.nem_last_error.restype = C.c_char_p
@@ -423,6 +426,14 @@ class Sim:
         _check(self.h, lib().nem_step_learned(C.c_void_p(self.h), C.c_void_p(mlp.h), n_macro, mult, tau,
                                               C.byref(nfb), C.byref(mx)), "nem_step_learned")
         return nfb.value, mx.value
+
+    def autotune(self, steps: int = 5):
+        """Pick the fastest (tile, lanes per particle) on the current state; returns (tile, lpp, ms/step)."""
+        t, l = C.c_int32(0), C.c_int32(0)
+        ms = C.c_double(0)
+        _check(self.h, lib().nem_autotune(C.c_void_p(self.h), steps, C.byref(t), C.byref(l), C.byref(ms)),
+               "nem_autotune")
+        return t.value, l.value, ms.value
 
     def set_option(self, key: int, value: int):
         nem_set_option(self.h, key, value)

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnematic_sph.so")
-SOURCES = ["nem_api.hip", "nem_passes.hip", "nem_sort.hip", "nem_grid.hip", "nem_mlp.hip", "nem_learn.hip"]
+SOURCES = ["nem_api.hip", "nem_passes.hip", "nem_sort.hip", "nem_grid.hip", "nem_mlp.hip", "nem_learn.hip", "nem_tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

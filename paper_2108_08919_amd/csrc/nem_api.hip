@@ -169,7 +169,7 @@ SortArgs sort_args(nem_sim* s, const unsigned* gate) {
 StepArgs step_args(nem_sim* s) {
   StepArgs a;
   const int c = s->parity, x = 1 - s->parity;
-  a.reps = s->d_reps; a.work = s->d_work; a.nwork = s->nwork; a.T = s->T; a.lpp = s->LPP;
+  a.reps = s->d_reps; a.work = s->d_work; a.nwork = s->nwork; a.T = s->T; a.lpp = s->LPP; a.grid = s->persist;
   a.cell_start = s->cell_start; a.ncells = s->ncells; a.ntot = s->ntot;
   a.off_cur = s->off[c]; a.off_nxt = s->off[x]; a.offlo = s->offlo; a.u = s->u;
   a.q_cur = s->q[c]; a.q_nxt = s->q[x]; a.acc = s->acc; a.drho = s->drho; a.cell = s->cell;
@@ -281,7 +281,8 @@ void drop_graphs(nem_sim* s) {
     if (g) { hipGraphExecDestroy(g); g = nullptr; }
 }
 
-// Capture the step of each parity into a graph (once per configuration).
+// Capture graph_steps consecutive steps starting at each parity into a graph
+// (once per configuration). No memset nodes: every clear is a kernel.
 int capture_graphs(nem_sim* s) {
   if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
   const int saved = s->parity;
@@ -291,7 +292,11 @@ int capture_graphs(nem_sim* s) {
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     const int timing = s->timing;
     s->timing = 0;
-    int rc = enqueue_step(s, s->cap_stream);
+    int rc = NEM_OK;
+    for (int k = 0; k < s->graph_steps && !rc; ++k) {
+      rc = enqueue_step(s, s->cap_stream);
+      s->parity ^= 1;
+    }
     s->timing = timing;
     hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
     if (rc) { if (g) hipGraphDestroy(g); s->parity = saved; return rc; }
@@ -350,13 +355,18 @@ int run_steps(nem_sim* s, int64_t nsteps) {
     int rc = capture_graphs(s);
     if (rc) { drop_graphs(s); return rc; }
   }
-  for (int64_t it = 0; it < nsteps; ++it) {
-    if (graph) {
+  int64_t it = 0;
+  if (graph) {
+    // whole chunks of graph_steps steps; the parity after a chunk flips only
+    // when the chunk length is odd
+    for (; it + s->graph_steps <= nsteps; it += s->graph_steps) {
       HIPCHK(hipGraphLaunch(s->graph[s->parity], s->stream));
-    } else {
-      int rc = enqueue_step(s, s->stream);
-      if (rc) return rc;
+      if (s->graph_steps & 1) s->parity ^= 1;
     }
+  }
+  for (; it < nsteps; ++it) {
+    int rc = enqueue_step(s, s->stream);
+    if (rc) return rc;
     s->parity ^= 1;
   }
   return NEM_OK;
@@ -693,8 +703,15 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
       s->timing = value ? 1 : 0;
       return NEM_OK;
     case NEM_OPT_GRAPH:
+      if (value < 0 || value > 4096) return NEM_E_INVAL;
       drop_graphs(s);
       s->use_graph = value ? 1 : 0;
+      s->graph_steps = value ? (int)value : 1;
+      return NEM_OK;
+    case NEM_OPT_PERSIST:
+      if (value < 0 || value > (1 << 20)) return NEM_E_INVAL;
+      drop_graphs(s);
+      s->persist = (int)value;
       return NEM_OK;
     default:
       return NEM_E_INVAL;

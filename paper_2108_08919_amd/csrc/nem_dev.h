@@ -48,6 +48,7 @@ struct StepArgs {
   const int* work;        // 2 ints per work item: replica, tile index
   int nwork, T;           // work items, tile side in cells
   int lpp;                // lanes per particle in passes B-D (1, 2, 4)
+  int grid;               // 0: one workgroup per tile; > 0: persistent grid size
   const int* cell_start;  // [ncells + 1], particles sorted by (replica, cell, id)
   int ncells, ntot;
   const float2* off_cur;  // cell-relative position (high part) at r^{n+1/2}

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(WG) void k_deposit(const StepArgs a, int rep_only, 
   __shared__ float4 s_f[MP];   // ux, uy, qxx, qxy at the integer level
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
   if (rep != rep_only) return;
   const int ni = L.hdr[0], nj = L.hdr[1], nreg = L.hdr[3];
   const int S = L.cstart[nreg];

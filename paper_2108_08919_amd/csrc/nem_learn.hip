@@ -159,7 +159,7 @@ void free_snapshot(nem_sim* s) {
   S = nem_sim::Snap();
 }
 
-static int take_snapshot(nem_sim* s) {
+int take_snapshot(nem_sim* s) {
   auto& S = s->snap;
   const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
   if (!S.alloc) {
@@ -197,7 +197,7 @@ static int take_snapshot(nem_sim* s) {
   return NEM_OK;
 }
 
-static int restore_snapshot(nem_sim* s) {
+int restore_snapshot(nem_sim* s) {
   auto& S = s->snap;
   if (!S.valid) return NEM_E_STATE;
   const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;

@@ -176,8 +176,7 @@ __device__ __forceinline__ void flag(unsigned* flags, unsigned bit) { atomicOr(f
 // Common prologue: set up the tile, check LDS capacity. Returns false when the
 // workgroup has nothing to do (uniform across the workgroup).
 template <int T>
-__device__ __forceinline__ bool tile_begin(const StepArgs& a, TileLDS<T>& L, RepDev& R, int& rep) {
-  const int w = blockIdx.x;
+__device__ __forceinline__ bool tile_begin(const StepArgs& a, int w, TileLDS<T>& L, RepDev& R, int& rep) {
   if (w >= a.nwork) return false;
   rep = tile_setup<T>(a, w, L, R);
   const int S = L.cstart[L.hdr[3]];

@@ -26,6 +26,8 @@
 //   pass C  density filter (Eq. densityCorrection) and EoS (Eq. sphEos)
 //   pass D  pressure term (Eq. sphMomentum), corrector, APD displacement
 //           (Eq. APD) and the next step's predictor (Sec. 3.1), fused
+#include <algorithm>
+
 #include "nem_dev.h"
 #include "nem_pair.h"
 
@@ -83,13 +85,13 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
 
 // ------------------------------------------------------------------ pass A
 template <int T, int COMP>
-__global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
+__device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T>::MAXP];
   __shared__ uint32_t s_list[(KMAX / 2) * WG];  // lane-private list words, lane-major
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
   const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
 
 // ------------------------------------------------------------------ pass B
 template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
+__device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
   __shared__ float2 s_off[MP];
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
   __shared__ float s_rho[FORM == 1 ? MP : 1];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -328,14 +330,14 @@ __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
 
 // ------------------------------------------------------------------ pass C
 template <int T, int COMP>
-__global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
+__device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float s_dh[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
 
 // ------------------------------------------------------------------ pass D
 template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
+__device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T>::MAXP;
   __shared__ float2 s_off[MP];
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
   __shared__ float s_wmax[WG / 64];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -529,7 +531,7 @@ __global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
   if (threadIdx.x == 0) {
     float m = 0.0f;
     for (int w = 0; w < WG / 64; ++w) m = fmaxf(m, s_wmax[w]);
-    if (m > 0.0f) atomicMax(&a.umax_nxt[rep * UMAX_SLOTS + (blockIdx.x & (UMAX_SLOTS - 1))], __float_as_uint(m));
+    if (m > 0.0f) atomicMax(&a.umax_nxt[rep * UMAX_SLOTS + (w & (UMAX_SLOTS - 1))], __float_as_uint(m));
   }
   if (rebin) atomicOr(&a.flags[1], 1u);
   if (bad) flag(a.flags, ERR_NUMERIC);
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
   __shared__ float s_V[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* s
   __shared__ int s_id[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, L, R, rep)) return;
+  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
   if (rep != rep_only) return;
   const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
@@ -667,10 +669,30 @@ __global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* s
   }
 }
 
+// ---------------------------------------------------------------- kernels
+// One workgroup per tile, or fewer workgroups looping over the tiles
+// (persistent launch: StepArgs::grid > 0).
+template <int T, int COMP>
+__global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a<T, COMP>(a, w); __syncthreads(); }
+}
+template <int T, int COMP, int FORM, int EL>
+__global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL>(a, w); __syncthreads(); }
+}
+template <int T, int COMP>
+__global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP>(a, w); __syncthreads(); }
+}
+template <int T, int COMP, int FORM, int EL>
+__global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL>(a, w); __syncthreads(); }
+}
+
 // ------------------------------------------------------------- dispatch
 template <int T, int COMP, int FORM, int EL>
 static void launch4(int pass, const StepArgs& a, hipStream_t s) {
-  const dim3 grid(a.nwork), block(WG);
+  const dim3 grid(a.grid > 0 ? std::min(a.grid, a.nwork) : a.nwork), block(WG);
   switch (pass) {
     case 1: hipLaunchKernelGGL((k_pass_a<T, COMP>), grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL>), grid, block, 0, s, a); break;

@@ -37,6 +37,8 @@ struct nem_sim {
   int parity = 0;
   std::vector<char> has_state;
   int T = 4, LPP = 1, COMP = 1;
+  int persist = 0;        // > 0: persistent pass kernels with this many workgroups
+  int graph_steps = 1;    // steps per captured graph
   int timing = 0;
   struct EvRec { int pass; hipEvent_t a, b; };
   std::vector<hipEvent_t> ev_free;
@@ -86,5 +88,9 @@ int status_from_flags(nem_sim* s, unsigned f);
 int run_steps(nem_sim* s, int64_t nsteps);
 int upload_reps(nem_sim* s);
 void free_snapshot(nem_sim* s);
+int take_snapshot(nem_sim* s);
+int restore_snapshot(nem_sim* s);
+int build_work(nem_sim* s);
+void drop_graphs(nem_sim* s);
 
 }  // namespace nem_host

@@ -1,0 +1,174 @@
+"""Learned corrector: training data from the solver, training, evaluation.
+
+Every numerical step runs in the library (nem_samples, nem_mlp_fit_norm,
+nem_mlp_train, nem_step_learned, nem_diagnostics, nem_defects); this module
+only schedules the calls and collects the results.
+
+Workloads:
+* training: 16 replicas of a 256 x 256 lattice box with (zeta, K) drawn from
+  U[0.005, 0.04] x U[0.01, 0.08] (seeded), isotropic director start; at four
+  times t in {0.25, 0.75, 1.25, 1.75} every replica contributes the inputs and
+  the (4 dt fine) - (one 4 dt step) targets of a seeded subset of 16,384 of its
+  particles: 4 x 16 x 16,384 = 1,048,576 samples;
+* evaluation: the 1024 x 1024 box at zeta = K = 0.02 over t in [0, 2] from four
+  seeded isotropic starts: plain steps of dt = 1e-3 (reference), plain steps of
+  4 dt, and learned macro steps of 4 dt; the errors are those of the ensemble-
+  and time-averaged kinetic energy and defect density over t in [1, 2].
+
+Run: python -m paper_2108_08919_amd.learned  (prints one JSON line)
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+
+
+def _sim(params, n):
+    from . import Sim
+    return Sim(params, n)
+
+
+def training_set(side=256, replicas=16, times=(0.25, 0.75, 1.25, 1.75), per_replica=16384, mult=4, seed=0,
+                 dt=1e-3):
+    import torch
+    import workloads as wl
+    rng = np.random.default_rng(seed)
+    params, states = [], []
+    for r in range(replicas):
+        zeta = float(rng.uniform(0.005, 0.04))
+        K = float(rng.uniform(0.01, 0.08))
+        params.append(wl.Params(L=float(side), zeta=zeta, K=K, dt=dt))
+        states.append(wl.initial_state(side, 1.0, 1.0, seed=2000 + r, kind="isotropic"))
+    n = side * side
+    sim = _sim(params, [n] * replicas)
+    for r in range(replicas):
+        sim.set_state(r, states[r])
+    Xs, Ts = [], []
+    t = 0.0
+    for tk in times:
+        k = int(round((tk - t) / dt))
+        sim.step(k)
+        t = tk
+        X, T = sim.samples(mult)
+        pick = []
+        for r in range(replicas):
+            sel = rng.choice(n, per_replica, replace=False)
+            pick.append(torch.from_numpy(np.sort(sel) + r * n))
+        idx = torch.cat(pick).to(X.device)
+        Xs.append(X[idx])
+        Ts.append(T[idx])
+    sim.check()
+    sim.close()
+    return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
+
+
+def init_weights(seed=0):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases (flat FP32 vector)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in ((12, 64), (64, 64), (64, 5)):
+        lim = 1.0 / math.sqrt(i)
+        parts.append(rng.uniform(-lim, lim, size=i * o))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fit(X, T, epochs=20, batch=4096, lr=2e-3, seed=0):
+    """Train a network on (X, T); returns (mlp, final batch loss, tau) where tau
+    is the 99.9th percentile of the training corrections' norm (normalised)."""
+    import torch
+    from . import Mlp
+    m = Mlp()
+    m.set_weights(init_weights(seed))
+    m.fit_norm(X, T)
+    loss = m.train(X, T, epochs=epochs, batch=batch, lr=lr)
+    nm = torch.from_numpy(m.get_norm()).to(X.device)
+    Y = m.forward(X)
+    z = (Y - nm[24:29]) / nm[29:34]
+    tau = float(torch.quantile(z.norm(dim=1)[:: max(1, X.shape[0] // 200000)], 0.999).item())
+    return m, loss, tau
+
+
+def _observe(sim, side):
+    d = sim.diagnostics(0)
+    p, mi = sim.defects(0, side)
+    return d["ke"], (p + mi) / float(side * side)
+
+
+def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0), dt=1e-3, mult=4, every=0.1):
+    import torch
+    import workloads as wl
+    p = wl.Params(L=float(side), zeta=0.02, K=0.02, dt=dt)
+    n = side * side
+    res = {"plain": [], "plain_coarse": [], "learned": []}
+    times = {"plain": 0.0, "plain_coarse": 0.0, "learned": 0.0}
+    fallbacks = 0
+    n_obs = int(round((t_avg[1] - t_avg[0]) / every)) + 1
+    for s in seeds:
+        st = wl.initial_state(side, 1.0, 1.0, seed=3000 + s, kind="isotropic")
+        for mode in ("plain", "plain_coarse", "learned"):
+            q = p if mode != "plain_coarse" else p.replace(dt=mult * dt)
+            sim = _sim([q], [n])
+            sim.set_state(0, st)
+            # advance to the start of the averaging window, then observe every `every`
+            obs = []
+            t = 0.0
+            targets = [t_avg[0] + k * every for k in range(n_obs)]
+            for tk in targets:
+                span = tk - t
+                torch.cuda.synchronize()
+                c0 = time.perf_counter()
+                if mode == "plain":
+                    sim.step(int(round(span / dt)))
+                    sim.sync()
+                elif mode == "plain_coarse":
+                    sim.step(int(round(span / (mult * dt))))
+                    sim.sync()
+                else:
+                    nfb, _ = sim.step_learned(m, int(round(span / (mult * dt))), mult, tau)
+                    fallbacks += nfb
+                torch.cuda.synchronize()
+                times[mode] += time.perf_counter() - c0
+                t = tk
+                obs.append(_observe(sim, side))
+            sim.check()
+            sim.close()
+            res[mode].append(obs)
+    out = {}
+    ref = np.array(res["plain"])           # seeds x times x (ke, defects)
+    for mode in res:
+        a = np.array(res[mode])
+        ke, de = a[..., 0].mean(), a[..., 1].mean()
+        out[mode] = {"ke": float(ke), "defect_density": float(de), "seconds": times[mode]}
+        out[mode]["eps_ke"] = float(abs(ke - ref[..., 0].mean()) / ref[..., 0].mean())
+        out[mode]["eps_defects"] = float(abs(de - ref[..., 1].mean()) / ref[..., 1].mean())
+    out["speedup_learned_vs_plain"] = times["plain"] / times["learned"] if times["learned"] > 0 else None
+    out["speedup_coarse_vs_plain"] = times["plain"] / times["plain_coarse"] if times["plain_coarse"] > 0 else None
+    out["fallbacks"] = fallbacks
+    out["tau"] = tau
+    return out
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--seeds", type=int, default=4)
+    args = ap.parse_args()
+    t0 = time.perf_counter()
+    X, T = training_set()
+    t1 = time.perf_counter()
+    m, loss, tau = fit(X, T, epochs=args.epochs)
+    t2 = time.perf_counter()
+    ev = evaluate(m, tau, side=args.side, seeds=tuple(range(args.seeds)))
+    t3 = time.perf_counter()
+    print(json.dumps({"samples": int(X.shape[0]), "train_loss": loss, "t_samples_s": t1 - t0,
+                      "t_train_s": t2 - t1, "t_eval_s": t3 - t2, **ev}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

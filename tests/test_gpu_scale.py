@@ -1,0 +1,78 @@
+"""Parity at the benchmark's full size (2048 x 2048 box, 4,194,304 particles, the
+launch configuration bench.py times) and statistics parity on a 256 x 256 box
+over a longer horizon (kinetic energy, defect density and spectrum slope within
+2%)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import diag
+import workloads as wl
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import field_errors, gpu_run, run_oracle  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_08919_amd as P
+    P.lib()
+    yield
+
+
+def test_full_size_two_steps():
+    cfg = wl.config("C4")
+    p = cfg["params"]
+    s0 = wl.state_for(cfg, 0)
+    # a small velocity field so that every term (pressure, viscosity, APD) acts from step 1
+    ux, uy = wl.smooth_velocity(s0["x"], s0["y"], p.L, 1e-3, 7)
+    s0["ux"], s0["uy"] = ux, uy
+    print("oracle 2 steps at 4.2M particles", flush=True)
+    o, _ = run_oracle(p, s0, 2)
+    print("gpu", flush=True)
+    g, sim = gpu_run(p, s0, 2)
+    e = field_errors(g, o, s0, p.L)
+    print({k: f"{v:.3e}" for k, v in e.items()}, flush=True)
+    for k in ("u", "Q", "rho", "pos"):
+        assert e[k] <= 1e-5, (k, e[k])
+    assert e["disp"] <= 1e-4
+    sim.close()
+
+
+def test_statistics_256_box():
+    side = 256
+    p = wl.Params(L=float(side), zeta=0.02, K=0.02)
+    s0 = wl.initial_state(side, 1.0, 1.0, seed=4, kind="isotropic")
+    import paper_2108_08919_amd as P
+    sim = P.Sim([p], [side * side])
+    sim.set_state(0, s0)
+    ost = oracle.State(s0)
+    ke_g, ke_o, de_g, de_o, sl_g, sl_o = [], [], [], [], [], []
+    for _ in range(3):
+        sim.step(200)
+        oracle.step(p, ost, 200)
+        sim.check()
+        d = sim.diagnostics(0)
+        ke_g.append(d["ke"])
+        ke_o.append(oracle.diagnostics(p, ost)["ke"])
+        pl, mi = sim.defects(0, side)
+        de_g.append((pl + mi) / side ** 2)
+        f = ost.fields()
+        op, om = diag.defects(p, f["x"], f["y"], f["qxx"], f["qxy"], side)
+        de_o.append((op + om) / side ** 2)
+        _, sg = sim.spectrum(0, side)
+        _, so = diag.spectrum(p, f["x"], f["y"], f["ux"], f["uy"], side)
+        sl_g.append(sg); sl_o.append(so)
+    print("ke", ke_g, ke_o, "defects", de_g, de_o, "slope", sl_g, sl_o, flush=True)
+    assert np.mean(ke_g) == pytest.approx(np.mean(ke_o), rel=0.02)
+    assert np.mean(de_g) == pytest.approx(np.mean(de_o), rel=0.02)
+    assert np.mean(sl_g) == pytest.approx(np.mean(sl_o), rel=0.02)
+    sim.close()
