@@ -33,6 +33,26 @@ NEIGHBOURS = 44          # accepted pairs per particle on the h = 1.3 dx lattice
 HBM_PEAK = 8.0e12        # B/s, MI355X
 FP32_PEAK = 157.3e12     # FLOP/s, MI355X vector FP32 (packed FMA)
 
+# HBM bytes per launch measured with two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) on the default
+# configuration (2048^2 box, tile 4, 1 lane/particle, compensation 1), each scaled by what the same
+# counter reads for a 1 GiB device-to-device copy in the same run (fetch x 2.0, write x 1.0). They hold
+# for the kernel sources with this fingerprint only; otherwise `traffic` is reported as null.
+MEASURED_TRAFFIC = {
+    "fingerprint": "b5ff7b5db2e67350",
+    "config": (2048, 4, 1, 1),
+    "bytes": {"pass_a_volume": 529.88e6, "pass_b_rates": 765.87e6, "pass_c_eos": 530.43e6,
+              "pass_d_update": 934.42e6},
+}
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("nem_passes.hip", "nem_pair.h", "nem_dev.h"):
+        with open(os.path.join(ROOT, "paper_2108_08919_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -47,6 +67,9 @@ def main():
     ap.add_argument("--graph-check", action="store_true", help="also time the hipGraph replay path")
     ap.add_argument("--workload", choices=("box", "ensemble"), default="box",
                     help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device to device once "
+                         "(a kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -113,6 +136,16 @@ def main():
     bytes_step = sum(BYTES_PER_PARTICLE.values())
     flops_step = sum(NEIGHBOURS * FLOP_PER_PAIR[k] + FLOP_PER_PARTICLE[k] for k in FLOP_PER_PAIR)
 
+    traffic = None
+    hbm_measured = None
+    if (kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]
+            and (cfg["n_side"], args.tile, args.lpp, args.comp) == MEASURED_TRAFFIC["config"]):
+        tb = MEASURED_TRAFFIC["bytes"]
+        traffic = tb[dom]
+        hbm_measured = {"GB/s": sum(tb.values()) / (sum(avg[k] for k in tb) * 1e-3) / 1e9,
+                        "frac": sum(tb.values()) / (sum(avg[k] for k in tb) * 1e-3) / HBM_PEAK,
+                        "bytes_per_step": sum(tb.values())}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -142,7 +175,9 @@ def main():
                    "particles": n, "tile": args.tile, "lanes_per_particle": args.lpp,
                    "compensation": args.comp},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
+        "hbm_measured": hbm_measured,
         "hbm_frac_algorithmic": value * bytes_step / HBM_PEAK,
         "valu_frac_algorithmic": value * flops_step / FP32_PEAK,
         "bytes_per_particle_step": bytes_step,
@@ -152,6 +187,13 @@ def main():
         "cpu_baseline": cpu,
     }
     sim.close()
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
 
 

@@ -123,18 +123,27 @@ __device__ __forceinline__ KW quintic(const RepDev& R, float r2) {
   return k;
 }
 
-// Same without the derivative (passes that need W only).
-__device__ __forceinline__ float quintic_W(const RepDev& R, float r2) {
-  const float r = r2 * rsqrtf(r2);
+// W only, also returning 1/r and r.
+__device__ __forceinline__ float quintic_Wr(const RepDev& R, float r2, float& rinv, float& r) {
+  rinv = rsqrtf(r2);
+  r = r2 * rinv;
   const float b = r * R.hinv;
   const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
   const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
-  const float P5 = fmaf(15.0f * t1s * t1s, t1, fmaf(-6.0f * t2s * t2s, t2, t3s * t3s * t3));
+  const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
+  const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
   return R.a2 * P5;
 }
 
-// A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: plain partial sum per
-// stencil cell, partials added with Kahan compensation. COMP 2: Kahan
+// Same without the derivative (passes that need W only).
+__device__ __forceinline__ float quintic_W(const RepDev& R, float r2) {
+  float rinv, r;
+  return quintic_Wr(R, r2, rinv, r);
+}
+
+// A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: plain partial sums
+// over short chunks of pairs (a stencil cell in pass A, 16 listed pairs in
+// passes B-D), the partials added with Kahan compensation. COMP 2: Kahan
 // compensation on every pair term.
 template <int COMP>
 struct Acc {

@@ -58,7 +58,7 @@ __device__ __forceinline__ void listed_pair(uint32_t e, float cs, int jmax, cons
 }
 
 // Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
-// sub, sub+lpp, ...; flush() closes a compensation chunk every 8 pairs.
+// sub, sub+lpp, ...; flush() closes a compensation chunk every 16 pairs.
 template <typename Body, typename Flush>
 __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int ntot, int g, int cnt, int lpp,
                                             int sub, Body&& body, Flush&& flush) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
       const uint32_t w = p[(size_t)(k >> 1) * ntot];
       body(w & 0xFFFFu);
       body(w >> 16);
-      if ((k & 7) == 6) flush();
+      if ((k & 15) == 14) flush();
     }
     if (k < cnt) body(p[(size_t)(k >> 1) * ntot] & 0xFFFFu);
   } else {
@@ -77,18 +77,23 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
     for (int k = sub; k < cnt; k += lpp, ++it) {
       const uint32_t w = p[(size_t)(k >> 1) * ntot];
       body((k & 1) ? (w >> 16) : (w & 0xFFFFu));
-      if ((it & 7) == 7) flush();
+      if ((it & 15) == 15) flush();
     }
   }
   flush();
 }
 
 // ------------------------------------------------------------------ pass A
+// Phase 1 tests the candidates of the nine stencil cells and records the
+// accepted ones as one 64-bit mask per cell (bit b = b-th particle of the
+// cell; a cell holds at most 64 particles). Phase 2 expands the masks into
+// list entries in cell order; all lanes emit their k-th word together, so the
+// list stores coalesce.
 template <int T, int COMP>
 __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T>::MAXP];
-  __shared__ uint32_t s_list[(KMAX / 2) * WG];  // lane-private list words, lane-major
+  __shared__ unsigned long long s_mask[9 * WG];  // lane-private, cell-major
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, w, L, R, rep)) return;
@@ -107,41 +112,60 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
     Acc<COMP> sw, sx3, sy3, sr;
     sw.init(); sx3.init(); sy3.init(); sr.init();
     int cnt = 0;
-    uint32_t pend = 0;
+    bool big = false;
 #pragma unroll 1
     for (int cidx = 0; cidx < 9; ++cidx) {
       const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
       const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-      const int j1 = L.cstart[sc + 1];
+      const int j0 = L.cstart[sc], j1 = L.cstart[sc + 1];
+      if (j1 - j0 > 64) big = true;
+      const int jend = min(j1, j0 + 64);
       const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-      const uint32_t dir = ((uint32_t)(dx + 1) << 12) | ((uint32_t)(dy + 1) << 14);
-      for (int j = L.cstart[sc]; j < j1; ++j) {
+      unsigned long long m = 0ull;
+      for (int j = j0; j < jend; ++j) {
         const float2 oj = s_off[j];
         float rx, ry, r2;
         if (!pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) continue;
-        const KW k = quintic(R, r2);
-        sw.add(k.W);
-        const float r3 = k.rinv * k.rinv * k.rinv;
-        sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(k.r);
-        const uint32_t e = (uint32_t)j | dir;
-        if (cnt < KMAX) {
-          if (cnt & 1) s_list[(cnt >> 1) * WG + tid] = pend | (e << 16);
-          else pend = e;
-        }
-        ++cnt;
+        float rinv, r;
+        sw.add(quintic_Wr(R, r2, rinv, r));
+        const float r3 = rinv * rinv * rinv;
+        sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
+        m |= 1ull << (j - j0);
       }
+      s_mask[cidx * WG + tid] = m;
+      cnt += __popcll(m);
       sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
     }
     const int kept = min(cnt, KMAX);
-    if (kept & 1) s_list[(kept >> 1) * WG + tid] = pend;
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
-    if (cnt > KMAX) flag(a.flags, ERR_OVERFLOW);
+    if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
     a.V[g] = 1.0f / (R.W0 + sw.value());
     a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)kept);
     a.ncnt[g] = kept;
+    // phase 2: entries (LDS slot | stencil direction) in cell order
+    int c = -1, jb = 0;
+    unsigned long long m = 0ull;
+    uint32_t dir = 0;
     uint32_t* dst = a.nl + g;
-    for (int w = 0; w < ((kept + 1) >> 1); ++w) dst[(size_t)w * a.ntot] = s_list[w * WG + tid];
+    for (int k = 0; k < kept; k += 2) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (k + h >= kept) break;
+        while (m == 0ull && c < 8) {
+          ++c;
+          m = s_mask[c * WG + tid];
+          const int dx = c % 3, dy = c / 3;  // direction + 1
+          jb = L.cstart[L.slot[(lj + dy) * (ni + 2) + (li + dx)]];
+          dir = ((uint32_t)dx << 12) | ((uint32_t)dy << 14);
+        }
+        const int b = __builtin_ctzll(m);
+        m &= m - 1ull;
+        word |= ((uint32_t)(jb + b) | dir) << (16 * h);
+      }
+      dst[(size_t)(k >> 1) * a.ntot] = word;
+    }
   }
 }
 

@@ -21,9 +21,14 @@ from __future__ import annotations
 
 import json
 import math
+import sys
 import time
 
 import numpy as np
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def _sim(params, n):
@@ -137,6 +142,7 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
             sim.check()
             sim.close()
             res[mode].append(obs)
+            _log(f"evaluated seed {s} {mode}: {times[mode]:.2f} s cumulative")
     out = {}
     ref = np.array(res["plain"])           # seeds x times x (ke, defects)
     for mode in res:
@@ -162,8 +168,10 @@ def main():
     t0 = time.perf_counter()
     X, T = training_set()
     t1 = time.perf_counter()
+    _log(f"training set: {X.shape[0]} samples in {t1 - t0:.1f} s")
     m, loss, tau = fit(X, T, epochs=args.epochs)
     t2 = time.perf_counter()
+    _log(f"trained: loss {loss:.4g}, tau {tau:.3g}, {t2 - t1:.1f} s")
     ev = evaluate(m, tau, side=args.side, seeds=tuple(range(args.seeds)))
     t3 = time.perf_counter()
     print(json.dumps({"samples": int(X.shape[0]), "train_loss": loss, "t_samples_s": t1 - t0,
