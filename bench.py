@@ -38,10 +38,10 @@ FP32_PEAK = 157.3e12     # FLOP/s, MI355X vector FP32 (packed FMA)
 # counter reads for a 1 GiB device-to-device copy in the same run (fetch x 2.0, write x 1.0). They hold
 # for the kernel sources with this fingerprint only; otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "fingerprint": "b5ff7b5db2e67350",
+    "fingerprint": "ced90e2a9ab8f1c8",
     "config": (2048, 4, 1, 1),
-    "bytes": {"pass_a_volume": 529.88e6, "pass_b_rates": 765.87e6, "pass_c_eos": 530.43e6,
-              "pass_d_update": 934.42e6},
+    "bytes": {"pass_a_volume": 530.00e6, "pass_b_rates": 766.66e6, "pass_c_eos": 530.70e6,
+              "pass_d_update": 934.85e6},
 }
 
 

@@ -39,7 +39,9 @@ extern "C" {
 #define NEM_E_NOMEM (-2)     /* arena too small or allocation failed */
 #define NEM_E_HIP (-3)       /* HIP runtime error */
 #define NEM_E_NUMERIC (-4)   /* a non-finite value appeared in the state */
-#define NEM_E_OVERFLOW (-5)  /* a cell tile holds more particles than the LDS staging capacity */
+#define NEM_E_OVERFLOW (-5)  /* a cell tile exceeds the LDS staging capacity (24 particles per cell on
+                                average), a cell holds more than 48 particles, or a particle has more
+                                than 64 neighbours */
 #define NEM_E_SINGULAR (-6)  /* correction tensor not invertible; B = I was used */
 #define NEM_E_STATE (-7)     /* call order (e.g. step before set_state) */
 #define NEM_E_RANGE (-8)     /* an index fell outside its buffer; the access was skipped */

@@ -208,7 +208,10 @@ int read_flags(nem_sim* s, unsigned* f) {
 
 int status_from_flags(nem_sim* s, unsigned f) {
   if (f & ERR_RANGE) { s->err = "device index outside its buffer (access skipped)"; return NEM_E_RANGE; }
-  if (f & ERR_OVERFLOW) { s->err = "a tile holds more particles than the LDS staging capacity"; return NEM_E_OVERFLOW; }
+  if (f & ERR_OVERFLOW) {
+    s->err = "a tile or cell holds more particles than the LDS staging capacity, or a particle has more than 64 neighbours";
+    return NEM_E_OVERFLOW;
+  }
   if (f & ERR_NUMERIC) { s->err = "non-finite value in the state"; return NEM_E_NUMERIC; }
   if (f & ERR_SINGULAR) { s->err = "singular correction tensor (B = I used)"; return NEM_E_SINGULAR; }
   return NEM_OK;
@@ -390,7 +393,7 @@ const char* nem_strerror(int code) {
     case NEM_E_NOMEM: return "not enough memory";
     case NEM_E_HIP: return "HIP runtime error";
     case NEM_E_NUMERIC: return "non-finite value in the state";
-    case NEM_E_OVERFLOW: return "cell tile over LDS capacity";
+    case NEM_E_OVERFLOW: return "cell tile, cell or neighbour list over capacity";
     case NEM_E_SINGULAR: return "singular correction tensor";
     case NEM_E_STATE: return "wrong call order";
     case NEM_E_RANGE: return "device index out of range";

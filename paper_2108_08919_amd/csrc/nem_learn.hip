@@ -43,14 +43,32 @@ __device__ inline int rep_of(const RepDev* reps, int R, int k) {
   return lo;
 }
 
+// Max of v over the workgroup (all threads call it; v >= 0), then one atomic
+// into this workgroup's max-speed slot of replica r.
+__device__ __forceinline__ void block_speed_max(unsigned* umax_cur, int r, float v) {
+  __shared__ float red[4];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    if (m > 0.0f) atomicMax(&umax_cur[r * UMAX_SLOTS + (blockIdx.x & (UMAX_SLOTS - 1))], __float_as_uint(m));
+  }
+}
+
 // Change every replica's time step by `factor`: recover r^n, u^n from the
 // stored prediction (made with the old dt) and predict again with the new dt.
 // Positions move by a few rounding units at most; the max-speed slots of the
-// current parity are refilled (cleared by the caller).
-__global__ void k_repredict(SortArgs s, float factor, unsigned* umax_cur) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
-    const int r = rep_of(s.reps, s.R, k);
-    const float dto = s.reps[r].dt, dtn = dto * factor;
+// current parity are refilled (cleared by the caller). Grid: (chunks, R) of
+// 256 threads; blockIdx.y is the replica.
+__global__ __launch_bounds__(256) void k_repredict(SortArgs s, float factor, unsigned* umax_cur) {
+  const int r = blockIdx.y;
+  const RepDev& R = s.reps[r];
+  const float dto = R.dt, dtn = dto * factor;
+  float vmax = 0.0f;
+  for (int k = R.part_base + blockIdx.x * blockDim.x + threadIdx.x; k < R.part_base + R.n;
+       k += gridDim.x * blockDim.x) {
     const float2 u = s.u[k], ac = s.acc[k], o = s.off[k], lo = s.offlo[k];
     const float unx = (u.x - 0.5f * dto * ac.x) + 0.5f * dtn * ac.x;
     const float uny = (u.y - 0.5f * dto * ac.y) + 0.5f * dtn * ac.y;
@@ -66,8 +84,9 @@ __global__ void k_repredict(SortArgs s, float factor, unsigned* umax_cur) {
     s.off[k] = nh;
     s.offlo[k] = nl;
     s.u[k] = make_float2(unx, uny);
-    atomicMax(&umax_cur[r * UMAX_SLOTS + (k & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(unx * unx + uny * uny)));
+    vmax = fmaxf(vmax, sqrtf(unx * unx + uny * uny));
   }
+  block_speed_max(umax_cur, r, vmax);
 }
 
 // (Qxx, Qxy, Qyy, ux, uy) at the integer level into out[(part_base + id) * 5].
@@ -90,15 +109,16 @@ __global__ void k_sub(float* T, const float* C, int64_t n) {
     T[k] -= C[k];
 }
 
-// Add the network's corrections Y[(part_base + id) * 5] to Q (projected on
-// traceless tensors) and u; refill the max-speed slots (cleared by the caller).
-__global__ void k_correct(SortArgs s, const float* Y, unsigned* umax_cur) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
-    const int r = rep_of(s.reps, s.R, k);
-    const RepDev& R = s.reps[r];
-    const int id = s.id[k];
-    if (id < 0 || id >= R.n) { atomicOr(s.flags, ERR_RANGE); continue; }
-    const float* y = Y + (size_t)(R.part_base + id) * 5;
+// Add the network's corrections Y[k * 5] (storage order) to Q (projected on
+// traceless tensors) and u; refill the max-speed slots (cleared by the
+// caller). Grid as k_repredict.
+__global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, unsigned* umax_cur) {
+  const int r = blockIdx.y;
+  const RepDev& R = s.reps[r];
+  float vmax = 0.0f;
+  for (int k = R.part_base + blockIdx.x * blockDim.x + threadIdx.x; k < R.part_base + R.n;
+       k += gridDim.x * blockDim.x) {
+    const float* y = Y + (size_t)k * 5;
     float2 q = s.q[k], u = s.u[k];
     q.x += 0.5f * (y[0] - y[2]);
     q.y += y[1];
@@ -119,11 +139,33 @@ __global__ void k_correct(SortArgs s, const float* Y, unsigned* umax_cur) {
     }
     s.off[k] = nh;
     s.offlo[k] = nl;
-    atomicMax(&umax_cur[r * UMAX_SLOTS + (k & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(u.x * u.x + u.y * u.y)));
+    vmax = fmaxf(vmax, sqrtf(u.x * u.x + u.y * u.y));
+  }
+  block_speed_max(umax_cur, r, vmax);
+}
+
+// dst[(part_base + id) * w + c] = src[k * w + c]: rows from storage order to
+// original particle order.
+__global__ void k_rows_by_id(SortArgs s, const float* src, float* dst, int w) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s.ntot; k += gridDim.x * blockDim.x) {
+    const int r = rep_of(s.reps, s.R, k);
+    const RepDev& R = s.reps[r];
+    const int id = s.id[k];
+    if (id < 0 || id >= R.n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const float* a = src + (size_t)k * w;
+    float* b = dst + (size_t)(R.part_base + id) * w;
+    for (int c = 0; c < w; ++c) b[c] = a[c];
   }
 }
 
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+// (chunks, replicas) grid for the per-replica kernels.
+static dim3 rep_grid(const nem_sim* s) {
+  int64_t nmax = 1;
+  for (const auto& R : s->reps) nmax = std::max<int64_t>(nmax, R.n);
+  return dim3((unsigned)std::min<int64_t>((nmax + 255) / 256, 1024), (unsigned)s->R);
+}
 
 }  // namespace nem
 
@@ -172,7 +214,7 @@ int take_snapshot(nem_sim* s) {
     HIPCHK(hipMalloc((void**)&S.id, sizeof(int) * N));
     HIPCHK(hipMalloc((void**)&S.cell, sizeof(int) * N));
     HIPCHK(hipMalloc((void**)&S.cell_start, sizeof(int) * (C + 1)));
-    HIPCHK(hipMalloc((void**)&S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS));
+    HIPCHK(hipMalloc((void**)&S.umax, sizeof(unsigned) * (s->R * UMAX_SLOTS + 1)));  // + rebin request
     S.alloc = true;
   }
   const int p = s->parity;
@@ -188,8 +230,7 @@ int take_snapshot(nem_sim* s) {
   HIPCHK(hipMemcpyAsync(S.cell_start, s->cell_start, sizeof(int) * (C + 1), d2d, s->stream));
   HIPCHK(hipMemcpyAsync(S.umax, s->umax + (size_t)p * s->R * UMAX_SLOTS, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
                         s->stream));
-  HIPCHK(hipMemcpyAsync(S.flags, s->flags, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpyAsync(S.umax + s->R * UMAX_SLOTS, s->flags + 1, sizeof(unsigned), d2d, s->stream));
   S.parity = p;
   S.dt.resize(s->R);
   for (int r = 0; r < s->R; ++r) S.dt[r] = s->reps[r].dt;
@@ -214,12 +255,8 @@ int restore_snapshot(nem_sim* s) {
   HIPCHK(hipMemcpyAsync(s->cell_start, S.cell_start, sizeof(int) * (C + 1), d2d, s->stream));
   HIPCHK(hipMemcpyAsync(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
                         s->stream));
-  // keep the sticky error bits, restore the rebin request
-  unsigned f[2];
-  HIPCHK(hipMemcpyAsync(f, s->flags, sizeof(f), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
-  f[1] = S.flags[1];
-  HIPCHK(hipMemcpyAsync(s->flags, f, sizeof(f), hipMemcpyHostToDevice, s->stream));
+  // keep the sticky error bits (flags[0]), restore the rebin request (flags[1])
+  HIPCHK(hipMemcpyAsync(s->flags + 1, S.umax + s->R * UMAX_SLOTS, sizeof(unsigned), d2d, s->stream));
   s->parity = p;
   for (int r = 0; r < s->R; ++r) s->reps[r].dt = S.dt[r];
   int rc = upload_reps(s);
@@ -233,7 +270,7 @@ static int scale_dt(nem_sim* s, float factor) {
   unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
   HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream));
   SortArgs a = sort_args(s, nullptr);
-  hipLaunchKernelGGL(k_repredict, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, factor, um);
+  hipLaunchKernelGGL(k_repredict, rep_grid(s), dim3(256), 0, s->stream, a, factor, um);
   HIPCHK(hipGetLastError());
   for (auto& R : s->reps) R.dt *= factor;
   return upload_reps(s);
@@ -435,17 +472,25 @@ int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
     if (!s->has_state[r]) return NEM_E_STATE;
   int rc = take_snapshot(s);
   if (rc) return rc;
-  float* coarse = nullptr;
-  HIPCHK(hipMalloc((void**)&coarse, sizeof(float) * 5 * (size_t)s->ntot));
-  // one step of mult*dt with the inputs captured
+  float *coarse = nullptr, *xs = nullptr;
+  const hipError_t e1 = hipMalloc((void**)&coarse, sizeof(float) * 5 * (size_t)s->ntot);
+  const hipError_t e2 = hipMalloc((void**)&xs, sizeof(float) * 12 * (size_t)s->ntot);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipFree(coarse);
+    hipFree(xs);
+    return hip_fail(s, e1 != hipSuccess ? e1 : e2, "hipMalloc (sample buffers)");
+  }
+  // one step of mult*dt with the inputs captured (storage order), then put
+  // them in original particle order
   rc = scale_dt(s, (float)mult);
   if (!rc) {
-    s->feat = X;
+    s->feat = xs;
     rc = run_steps(s, 1);
     s->feat = nullptr;
   }
   if (!rc) {
     SortArgs a = sort_args(s, nullptr);
+    hipLaunchKernelGGL(k_rows_by_id, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, (const float*)xs, X, 12);
     hipLaunchKernelGGL(k_export_qu, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, coarse);
   }
   // mult steps of dt from the same state
@@ -460,6 +505,7 @@ int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
   if (!rc) rc = restore_snapshot(s);
   hipStreamSynchronize(s->stream);
   hipFree(coarse);
+  hipFree(xs);
   if (rc) return rc;
   return check_flags(s);
 }
@@ -505,7 +551,7 @@ int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, doub
     unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
     HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream));
     SortArgs a = sort_args(s, nullptr);
-    hipLaunchKernelGGL(k_correct, dim3(grid_for(s->ntot)), dim3(256), 0, s->stream, a, Y, um);
+    hipLaunchKernelGGL(k_correct, rep_grid(s), dim3(256), 0, s->stream, a, Y, um);
     HIPCHK(hipGetLastError());
   }
   if (!rc) rc = scale_dt(s, 1.0f / (float)mult);

@@ -58,7 +58,15 @@ __device__ __forceinline__ bf16x8 frag_bt(const bf16* S, int ld, int k0, int n0,
   return frag_a(S, ld, n0, k0, l);
 }
 
-struct MlpNorm { float xm[NI], xs[NI], ym[NO], ys[NO]; };
+struct MlpNorm { float xm[NI], xs[NI], xr[NI], ym[NO], ys[NO]; };  // xr = 1 / xs
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1) on the hardware exp2 and reciprocal (about
+// 1e-7 absolute error, far below the BF16 rounding of the activations it
+// feeds); exp overflow gives +1, underflow -1.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // 2 log2(e) x
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
 
 // BF16 copies of the weights in LDS, zero-padded to MFMA shapes.
 struct WLds {
@@ -108,7 +116,7 @@ __device__ __forceinline__ void load_x(const float* X, int64_t n, int64_t base, 
     const int64_t s = base + r;
     if (c < NI && s < n) {
       const int64_t src = idx ? idx[s] : s;
-      v = (X[src * NI + c] - nm.xm[c]) / nm.xs[c];
+      v = (X[src * NI + c] - nm.xm[c]) * nm.xr[c];
     }
     a.x[t] = (bf16)v;
   }
@@ -125,7 +133,7 @@ __device__ __forceinline__ void forward32(const WLds& W, ActF& a, int l, f32x4 y
       acc = mfma(frag_a(a.x, 32, rt * 16, 0, l), frag_b(W.w1, NH, 0, nt * 16, l), acc);
       const int col = nt * 16 + (l & 15);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a.h1[(rt * 16 + (l >> 4) * 4 + i) * NH + col] = (bf16)tanhf(acc[i] + W.b1[col]);
+      for (int i = 0; i < 4; ++i) a.h1[(rt * 16 + (l >> 4) * 4 + i) * NH + col] = (bf16)fast_tanh(acc[i] + W.b1[col]);
     }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -138,7 +146,7 @@ __device__ __forceinline__ void forward32(const WLds& W, ActF& a, int l, f32x4 y
         acc = mfma(frag_a(a.h1, NH, rt * 16, kc * 32, l), frag_b(W.w2, NH, kc * 32, nt * 16, l), acc);
       const int col = nt * 16 + (l & 15);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a.h2[(rt * 16 + (l >> 4) * 4 + i) * NH + col] = (bf16)tanhf(acc[i] + W.b2[col]);
+      for (int i = 0; i < 4; ++i) a.h2[(rt * 16 + (l >> 4) * 4 + i) * NH + col] = (bf16)fast_tanh(acc[i] + W.b2[col]);
     }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -157,40 +165,121 @@ __device__ __forceinline__ void forward32(const WLds& W, ActF& a, int l, f32x4 y
 // Y (n x 5): corrections in physical units (denormalised). maxnorm (may be
 // NULL): max over samples of the Euclidean norm of the normalised output,
 // as float bits.
+//
+// Inference keeps everything in registers by computing each layer transposed,
+// H^T = W^T X^T: the weights are the A operand (preloaded once per wave as
+// fragments), the 16 samples of an iteration are the N dimension, and the
+// output tile D[4g + i][c] (g = l / 16, c = l % 16) holds hidden units
+// 16 mt + 4g + i of sample c. The next layer's B operand needs, in lane l,
+// K slots 8g..8g+7 of sample c; numbering the hidden units so that K slot
+// 8g + i of K tile kc is unit 16 (2 kc + i / 4) + 4g + i % 4 makes that
+// operand exactly the lane's own D registers of tiles 2kc and 2kc+1 (the
+// weights' K index uses the same numbering), so no data moves between lanes.
+__device__ __forceinline__ int unit_of(int kc, int g, int i) { return 16 * (2 * kc + (i >> 2)) + 4 * g + (i & 3); }
+
+// X rows are 48 bytes; VEC reads them as float4 (X 16-byte aligned).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P, MlpNorm nm,
                                                      const float* __restrict__ X, int64_t n, float* Y,
                                                      unsigned* maxnorm) {
-  __shared__ WLds W;
-  __shared__ ActF act[4];
-  load_weights(P, W, false);
-  __syncthreads();
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  ActF& a = act[wv];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+  // this lane's input features 8g + i (i < nf) and their normalisation
+  const int nf = g == 0 ? 8 : (g == 1 ? NI - 8 : 0);
+  float xm8[8], xr8[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    xm8[i] = i < nf ? nm.xm[8 * g + i] : 0.0f;
+    xr8[i] = i < nf ? nm.xr[8 * g + i] : 0.0f;
+  }
+  bf16x8 a1[4], a2[4][2], a3[2];
+  float bb1[4][4], bb2[4][4], bb3[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = 8 * g + i;
+      a1[mt][i] = (bf16)(k < NI ? P[OFF_W1 + k * NH + 16 * mt + c] : 0.0f);
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a2[mt][kc][i] = (bf16)P[OFF_W2 + unit_of(kc, g, i) * NH + 16 * mt + c];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bb1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
+      bb2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
+    }
+  }
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a3[kc][i] = (bf16)(c < NO ? P[OFF_W3 + unit_of(kc, g, i) * NO + c] : 0.0f);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bb3[i] = (4 * g + i < NO) ? P[OFF_B3 + 4 * g + i] : 0.0f;
+
   float mx = 0.0f;
-  const int64_t nblk = (n + ROWS - 1) / ROWS;
+  const int64_t nblk = (n + 15) / 16;
   for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nblk; b += (int64_t)gridDim.x * 4) {
-    const int64_t base = b * ROWS;
-    load_x(X, n, base, nm, nullptr, a, l);
-    __builtin_amdgcn_wave_barrier();
-    f32x4 y[2];
-    forward32(W, a, l, y);
-    const int col = l & 15;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t s = base + rt * 16 + (l >> 4) * 4 + i;
-        const float v = y[rt][i];
-        // squared norm over the 5 outputs of this row: lanes col 0..4 of the same group
-        float sq = (col < NO) ? v * v : 0.0f;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) sq += __shfl_xor(sq, o, 64);
-        if (s < n) {
-          if (col < NO) Y[s * NO + col] = v * nm.ys[col] + nm.ym[col];
-          mx = fmaxf(mx, sqrtf(sq));
-        }
+    const int64_t s = b * 16 + c;
+    const float* xrow = X + (s < n ? s : n - 1) * NI + 8 * g;  // clamped: in bounds for every lane
+    float xv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (VEC) {
+      if (nf > 0) {
+        const float4 v0 = *reinterpret_cast<const float4*>(xrow);
+        xv[0] = v0.x; xv[1] = v0.y; xv[2] = v0.z; xv[3] = v0.w;
       }
-    __builtin_amdgcn_wave_barrier();
+      if (nf > 4) {
+        const float4 v1 = *reinterpret_cast<const float4*>(xrow + 4);
+        xv[4] = v1.x; xv[5] = v1.y; xv[6] = v1.z; xv[7] = v1.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < nf) xv[i] = xrow[i];
+    }
+    const float keep = s < n ? 1.0f : 0.0f;
+    bf16x8 xb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xb[i] = (bf16)(keep * ((xv[i] - xm8[i]) * xr8[i]));
+    f32x4 d1[4], d2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      d1[mt] = mfma(a1[mt], xb, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d1[mt][i] = fast_tanh(d1[mt][i] + bb1[mt][i]);
+    }
+    bf16x8 hb[2];
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { hb[kc][i] = (bf16)d1[2 * kc][i]; hb[kc][4 + i] = (bf16)d1[2 * kc + 1][i]; }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      d2[mt] = mfma(a2[mt][0], hb[0], f32x4{0.f, 0.f, 0.f, 0.f});
+      d2[mt] = mfma(a2[mt][1], hb[1], d2[mt]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d2[mt][i] = fast_tanh(d2[mt][i] + bb2[mt][i]);
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { hb[kc][i] = (bf16)d2[2 * kc][i]; hb[kc][4 + i] = (bf16)d2[2 * kc + 1][i]; }
+    f32x4 y = mfma(a3[0], hb[0], f32x4{0.f, 0.f, 0.f, 0.f});
+    y = mfma(a3[1], hb[1], y);
+    // lane (g, c) holds outputs 4g + i of sample s: g = 0 -> 0..3, g = 1 -> 4
+    float sq = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = 4 * g + i;
+      y[i] += bb3[i];
+      if (o < NO) {
+        sq += y[i] * y[i];
+        if (s < n) Y[s * NO + o] = y[i] * nm.ys[o] + nm.ym[o];
+      }
+    }
+    sq += __shfl_xor(sq, 16, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    if (s < n) mx = fmaxf(mx, sqrtf(sq));
   }
   if (maxnorm) {
 #pragma unroll
@@ -414,17 +503,20 @@ int mlp_backward_waves(int64_t B) {
 void launch_mlp_forward(const float* P, const float* norm, const float* X, int64_t n, float* Y, unsigned* maxnorm,
                         hipStream_t s) {
   MlpNorm nm;
-  for (int i = 0; i < NI; ++i) { nm.xm[i] = norm[i]; nm.xs[i] = norm[NI + i]; }
+  for (int i = 0; i < NI; ++i) { nm.xm[i] = norm[i]; nm.xs[i] = norm[NI + i]; nm.xr[i] = 1.0f / norm[NI + i]; }
   for (int i = 0; i < NO; ++i) { nm.ym[i] = norm[2 * NI + i]; nm.ys[i] = norm[2 * NI + NO + i]; }
-  const int64_t nblk = (n + ROWS - 1) / ROWS;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nblk + 3) / 4, 2048));
-  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(256), 0, s, P, nm, X, n, Y, maxnorm);
+  const int64_t nblk = (n + 15) / 16;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nblk + 3) / 4, 1024));
+  if (((uintptr_t)X & 15u) == 0)
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(grid), dim3(256), 0, s, P, nm, X, n, Y, maxnorm);
+  else
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(grid), dim3(256), 0, s, P, nm, X, n, Y, maxnorm);
 }
 
 void launch_mlp_backward(const float* P, const float* norm, const float* X, const float* T, const int64_t* idx,
                          int64_t B, float* partial, float* lossp, int nwaves, hipStream_t s) {
   MlpNorm nm;
-  for (int i = 0; i < NI; ++i) { nm.xm[i] = norm[i]; nm.xs[i] = norm[NI + i]; }
+  for (int i = 0; i < NI; ++i) { nm.xm[i] = norm[i]; nm.xs[i] = norm[NI + i]; nm.xr[i] = 1.0f / norm[NI + i]; }
   for (int i = 0; i < NO; ++i) { nm.ym[i] = norm[2 * NI + i]; nm.ys[i] = norm[2 * NI + NO + i]; }
   hipLaunchKernelGGL(k_mlp_backward, dim3(nwaves / 2), dim3(128), 0, s, P, nm, X, T, idx, B, partial, lossp);
 }

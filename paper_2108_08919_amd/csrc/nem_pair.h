@@ -20,6 +20,7 @@ struct TileLDS {
   int gstart[TileCfg<T>::NSC];      // first global particle of each staged cell
   int slot[TileCfg<T>::NSC];        // region index (lj+1)*(ni+2)+(li+1) -> staged cell
   int hdr[8];                       // ni, nj, nint, nreg
+  float2 shift[16];                 // image shift of stencil direction (dx+1) | (dy+1) << 2
 };
 
 // Staged-cell index of region cell (li, lj), li in [-1, ni], lj in [-1, nj].
@@ -58,6 +59,7 @@ __device__ int tile_setup(const StepArgs& a, int w, TileLDS<T>& L, RepDev& R) {
     cnt[st] = max(s1 - s0, 0);
   }
   if (t == 0) { L.hdr[0] = ni; L.hdr[1] = nj; L.hdr[2] = ni * nj; L.hdr[3] = nreg; }
+  if (t < 16) L.shift[t] = make_float2((float)(1 - (t & 3)) * R.cs, (float)(1 - (t >> 2)) * R.cs);
   __syncthreads();
   if (t < 64) {  // wave 0: exclusive scan of up to 128 counts, two per lane
     const int i0 = 2 * t, i1 = 2 * t + 1;
@@ -107,10 +109,13 @@ __device__ __forceinline__ bool pair_accept(float oix, float oiy, float ojx, flo
 
 // Quintic spline of support 3h (2D): W and F = (dW/dr)/r, so that
 // grad_i W_ij = F r_ij.
+// r2 is positive and far above the FP32 denormal range for every accepted pair
+// (particles never come within 1e-19 of each other), so the hardware
+// reciprocal square root is used without the denormal rescaling of rsqrtf.
 struct KW { float rinv, r, W, F; };
 __device__ __forceinline__ KW quintic(const RepDev& R, float r2) {
   KW k;
-  k.rinv = rsqrtf(r2);
+  k.rinv = __builtin_amdgcn_rsqf(r2);
   k.r = r2 * k.rinv;
   const float b = k.r * R.hinv;
   const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
@@ -125,7 +130,7 @@ __device__ __forceinline__ KW quintic(const RepDev& R, float r2) {
 
 // W only, also returning 1/r and r.
 __device__ __forceinline__ float quintic_Wr(const RepDev& R, float r2, float& rinv, float& r) {
-  rinv = rsqrtf(r2);
+  rinv = __builtin_amdgcn_rsqf(r2);
   r = r2 * rinv;
   const float b = r * R.hinv;
   const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
@@ -141,10 +146,13 @@ __device__ __forceinline__ float quintic_W(const RepDev& R, float r2) {
   return quintic_Wr(R, r2, rinv, r);
 }
 
-// A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: plain partial sums
-// over short chunks of pairs (a stencil cell in pass A, 16 listed pairs in
-// passes B-D), the partials added with Kahan compensation. COMP 2: Kahan
-// compensation on every pair term.
+// A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: Kahan summation over
+// short chunks of pairs (a chunk is 16 listed pairs): terms are added plainly
+// into the chunk partial p, and at the end of the chunk p is added to the
+// running sum s with its rounding error recovered exactly (Fast2Sum) and
+// carried into the next chunk's partial. That is Kahan's update applied to the
+// chunk sums with the compensation held in p, so it costs two registers and
+// three operations per chunk. COMP 2: Kahan compensation on every pair term.
 template <int COMP>
 struct Acc {
   float s, c, p;
@@ -166,17 +174,18 @@ struct Acc {
     else { const float x = a * b; kahan(s, c, x); }
   }
   __device__ __forceinline__ void end_cell() {
-    if constexpr (COMP == 1) { kahan(s, c, p); p = 0.0f; }
+    if constexpr (COMP == 1) {
+#pragma clang fp contract(off)
+      const float t = s + p;
+      p = (s - t) + p;
+      s = t;
+    }
   }
   // This lane's compensated value.
-  __device__ __forceinline__ float value() const { return (COMP == 0) ? s : (s - c); }
-  // Value summed over the LPP lanes that share a particle.
-  template <int LPP>
-  __device__ __forceinline__ float total() const {
-    float v = (COMP == 0) ? s : (s - c);
-#pragma unroll
-    for (int o = 1; o < LPP; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+  __device__ __forceinline__ float value() const {
+    if constexpr (COMP == 0) return s;
+    else if constexpr (COMP == 1) return s + p;
+    else return s - c;
   }
 };
 

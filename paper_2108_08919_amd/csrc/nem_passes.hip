@@ -48,13 +48,12 @@ __device__ __forceinline__ float wave_sum(float v, int lpp) {
 
 // Pair geometry of a listed neighbour: same operations as the predicate, so the
 // vector and r^2 are bit-identical to those pass A accepted.
-__device__ __forceinline__ void listed_pair(uint32_t e, float cs, int jmax, const float2* s_off, float2 oi,
-                                            int& j, float& rx, float& ry, float& r2) {
+__device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int jmax, const float2* s_off,
+                                            float2 oi, int& j, float& rx, float& ry, float& r2) {
   j = min((int)(e & 0xFFFu), jmax);
-  const float sx = (float)(1 - (int)((e >> 12) & 3u)) * cs;
-  const float sy = (float)(1 - (int)((e >> 14) & 3u)) * cs;
+  const float2 sh = shift[(e >> 12) & 15u];
   const float2 oj = s_off[j];
-  pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, 3.4e38f, rx, ry, r2);
+  pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, 3.4e38f, rx, ry, r2);
 }
 
 // Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
@@ -84,16 +83,22 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
 }
 
 // ------------------------------------------------------------------ pass A
-// Phase 1 tests the candidates of the nine stencil cells and records the
-// accepted ones as one 64-bit mask per cell (bit b = b-th particle of the
-// cell; a cell holds at most 64 particles). Phase 2 expands the masks into
-// list entries in cell order; all lanes emit their k-th word together, so the
-// list stores coalesce.
+// Phase 1 runs the predicate over the candidates of the nine stencil cells and
+// records, per cell, one 64-bit word: the accepted particles as a mask in bits
+// 0-47 (bit b = b-th particle of the cell; a cell holds at most 48), the
+// cell's first LDS slot in bits 48-59 and the stencil direction code in bits
+// 60-63. Phase 2 walks the accepted pairs in cell order, all lanes taking their
+// k-th pair together: it sums the kernel terms and emits the list entries
+// (coalesced stores), so the kernel is evaluated for accepted pairs only.
+constexpr int CELL_MAX = 48;
+constexpr unsigned long long MASK48 = (1ull << 48) - 1ull;
+
 template <int T, int COMP>
 __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T>::MAXP];
   __shared__ unsigned long long s_mask[9 * WG];  // lane-private, cell-major
+  static_assert(TileCfg<T>::MAXP <= 4096, "LDS slot must fit 12 bits");
   RepDev R;
   int rep;
   if (!tile_begin<T>(a, w, L, R, rep)) return;
@@ -109,63 +114,70 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
     const int st = find_cell(L.cstart, nint, p);
     const int li = st % ni, lj = st / ni;
     const float2 oi = s_off[p];
-    Acc<COMP> sw, sx3, sy3, sr;
-    sw.init(); sx3.init(); sy3.init(); sr.init();
     int cnt = 0;
     bool big = false;
 #pragma unroll 1
     for (int cidx = 0; cidx < 9; ++cidx) {
-      const int dy = cidx / 3 - 1, dx = cidx % 3 - 1;
-      const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-      const int j0 = L.cstart[sc], j1 = L.cstart[sc + 1];
-      if (j1 - j0 > 64) big = true;
-      const int jend = min(j1, j0 + 64);
-      const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-      unsigned long long m = 0ull;
-      for (int j = j0; j < jend; ++j) {
-        const float2 oj = s_off[j];
+      const int dy = cidx / 3, dx = cidx % 3;  // direction + 1
+      const int sc = L.slot[(lj + dy) * (ni + 2) + (li + dx)];
+      const int j0 = L.cstart[sc];
+      const int nj = L.cstart[sc + 1] - j0;
+      if (nj > CELL_MAX) big = true;
+      const uint32_t code = (uint32_t)dx | ((uint32_t)dy << 2);
+      const float2 sh = L.shift[code];
+      uint32_t mlo = 0u, mhi = 0u;
+      const int n0 = min(nj, 32), n1 = min(nj, CELL_MAX);
+      for (int b = 0; b < n0; ++b) {
+        const float2 oj = s_off[j0 + b];
         float rx, ry, r2;
-        if (!pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) continue;
-        float rinv, r;
-        sw.add(quintic_Wr(R, r2, rinv, r));
-        const float r3 = rinv * rinv * rinv;
-        sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
-        m |= 1ull << (j - j0);
+        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) mlo |= 1u << b;
       }
-      s_mask[cidx * WG + tid] = m;
-      cnt += __popcll(m);
-      sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
+      for (int b = 32; b < n1; ++b) {
+        const float2 oj = s_off[j0 + b];
+        float rx, ry, r2;
+        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) mhi |= 1u << (b - 32);
+      }
+      s_mask[cidx * WG + tid] = ((unsigned long long)code << 60) | ((unsigned long long)j0 << 48) |
+                                ((unsigned long long)mhi << 32) | mlo;
+      cnt += __popc(mlo) + __popc(mhi);
     }
     const int kept = min(cnt, KMAX);
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
+    Acc<COMP> sw, sx3, sy3, sr;
+    sw.init(); sx3.init(); sy3.init(); sr.init();
+    int c = -1;
+    unsigned long long m = 0ull, x = 0ull;
+    uint32_t word = 0u;
+    uint32_t* dst = a.nl + g;
+    for (int k = 0; k < kept; ++k) {
+      while (m == 0ull && c < 8) {
+        ++c;
+        x = s_mask[c * WG + tid];
+        m = x & MASK48;
+      }
+      const uint32_t hi = (uint32_t)(x >> 48);  // code << 12 | first slot
+      const int j = (int)(hi & 0xFFFu) + __builtin_ctzll(m);
+      m &= m - 1ull;
+      const float2 sh = L.shift[hi >> 12];
+      const float2 oj = s_off[j];
+      float rx, ry, r2;
+      pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2);
+      float rinv, r;
+      sw.add(quintic_Wr(R, r2, rinv, r));
+      const float r3 = rinv * rinv * rinv;
+      sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
+      const uint32_t e = (uint32_t)j | (hi & 0xF000u);
+      if (k & 1) dst[(size_t)(k >> 1) * a.ntot] = word | (e << 16);
+      else word = e;
+      if ((k & 15) == 15) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
+    }
+    if (kept & 1) dst[(size_t)(kept >> 1) * a.ntot] = word;
+    sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
     a.V[g] = 1.0f / (R.W0 + sw.value());
     a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)kept);
     a.ncnt[g] = kept;
-    // phase 2: entries (LDS slot | stencil direction) in cell order
-    int c = -1, jb = 0;
-    unsigned long long m = 0ull;
-    uint32_t dir = 0;
-    uint32_t* dst = a.nl + g;
-    for (int k = 0; k < kept; k += 2) {
-      uint32_t word = 0;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (k + h >= kept) break;
-        while (m == 0ull && c < 8) {
-          ++c;
-          m = s_mask[c * WG + tid];
-          const int dx = c % 3, dy = c / 3;  // direction + 1
-          jb = L.cstart[L.slot[(lj + dy) * (ni + 2) + (li + dx)]];
-          dir = ((uint32_t)dx << 12) | ((uint32_t)dy << 14);
-        }
-        const int b = __builtin_ctzll(m);
-        m &= m - 1ull;
-        word |= ((uint32_t)(jb + b) | dir) << (16 * h);
-      }
-      dst[(size_t)(k >> 1) * a.ntot] = word;
-    }
   }
 }
 
@@ -226,7 +238,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       const int cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
         const KW k = quintic(R, r2);
         const float Vj = s_V[j];
         const float2 uj = s_u[j], qj = s_q[j];
@@ -336,17 +348,12 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
       }
-      if (a.feat) {  // learned-corrector inputs: Q, grad u, H, density, activity
-        const int idl = a.id[g];
-        if (idl >= 0 && idl < R.n) {
-          float* f = a.feat + (size_t)(R.part_base + idl) * 12;
-          f[0] = qa; f[1] = qb; f[2] = -qa;
-          f[3] = G11; f[4] = G12; f[5] = G21; f[6] = G22;
-          f[7] = Ha; f[8] = Hb; f[9] = -Ha;
-          f[10] = drho_n * R.inv_rho0; f[11] = R.zeta;
-        } else {
-          flag(a.flags, ERR_RANGE);
-        }
+      if (a.feat) {  // learned-corrector inputs (storage order): Q, grad u, H, density, activity
+        float* f = a.feat + (size_t)g * 12;
+        f[0] = qa; f[1] = qb; f[2] = -qa;
+        f[3] = G11; f[4] = G12; f[5] = G21; f[6] = G22;
+        f[7] = Ha; f[8] = Hb; f[9] = -Ha;
+        f[10] = drho_n * R.inv_rho0; f[11] = R.zeta;
       }
     }
   }
@@ -394,7 +401,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       const int cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
         sd.fma(s_dh[j], quintic_W(R, r2));
       }, [&]() { sd.end_cell(); });
     }
@@ -467,7 +474,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       const int cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
         const KW k = quintic(R, r2);
         const float c = (FORM == 0) ? s_V[j] * k.F : k.F;
         const float f = (Pi + s_P[j]) * c;
@@ -598,7 +605,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     Mxxa.init(); Mxya.init(); Myya.init(); Mxxb.init(); Mxyb.init(); Myyb.init();
     each_listed(a.nl, a.ntot, g, min(a.ncnt[g], KMAX), 1, 0, [&](uint32_t e) {
       int j; float rx, ry, r2;
-      listed_pair(e, R.cs, S - 1, s_off, oi, j, rx, ry, r2);
+      listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
       const KW k = quintic(R, r2);
       const float c = s_V[j] * k.F, cx = c * rx, cy = c * ry;
       const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;

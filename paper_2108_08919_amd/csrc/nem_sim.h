@@ -60,8 +60,7 @@ struct nem_sim {
     float2 *off = nullptr, *offlo = nullptr, *u = nullptr, *q = nullptr, *acc = nullptr;
     float* drho = nullptr;
     int *id = nullptr, *cell = nullptr, *cell_start = nullptr;
-    unsigned* umax = nullptr;
-    unsigned flags[2] = {0, 0};
+    unsigned* umax = nullptr;  // R * UMAX_SLOTS max-speed slots, then the rebin request
     int parity = 0;
     std::vector<float> dt;
   } snap;

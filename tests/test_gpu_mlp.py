@@ -170,3 +170,22 @@ def test_learned_step_fallback_is_fine_stepping():
     print(e, flush=True)
     assert e["u"] < 1e-5 and e["Q"] < 1e-6 and e["pos_abs_max"] < 1e-7
     sim.close(); sf.close(); m.close()
+
+
+def test_trained_network_reduces_q_correction_error():
+    """A network trained by the library's kernels on solver samples predicts the
+    Q part of the (4 fine steps) - (one 4 dt step) difference on held-out
+    boxes (other seeds and activity/elasticity draws): applying it leaves a
+    much smaller Q error than the plain 4 dt step. The velocity part is not a
+    function of the network's inputs (local Q, grad u, H, density, activity);
+    the network must at least not make it worse than no correction."""
+    from paper_2108_08919_amd import learned
+    X, T = learned.training_set(side=64, replicas=8, times=(0.1, 0.2, 0.3), per_replica=4096, seed=0)
+    m, loss, tau = learned.fit(X, T, epochs=10, batch=1024, lr=3e-3)
+    Xh, Th = learned.training_set(side=64, replicas=4, times=(0.15,), per_replica=4096, seed=1)
+    rel = learned.held_out_errors(m, Xh, Th)
+    print("held-out relative MSE", rel, "loss", loss, "tau", tau, flush=True)
+    assert max(rel[:3]) < 0.1
+    assert max(rel[3:]) < 1.2
+    assert tau > 0
+    m.close()
