@@ -21,6 +21,8 @@ Workloads:
 The fallback threshold tau is the 99.9th percentile of the training
 corrections' norm in the network's normalised output units; a macro step whose
 largest predicted correction norm exceeds it is replayed as 4 fine steps.
+Output components with no skill on the held-out boxes (relative MSE not below
+1) are switched off before the evaluation, so they contribute no correction.
 
 Run: python -m paper_2108_08919_amd.learned  (prints one JSON line)
 """
@@ -104,6 +106,25 @@ def fit(X, T, epochs=20, batch=4096, lr=2e-3, seed=0):
     return m, loss, tau
 
 
+def mask_unskilled(m, rel, threshold=1.0):
+    """Switch off the output components whose held-out relative MSE is not
+    below `threshold` (no better than no correction): their last-layer weights,
+    bias and output mean are set to zero, so the network returns exactly zero
+    for them. Returns the masked component indices."""
+    w = m.get_weights()
+    nm = m.get_norm()
+    off_w3 = 12 * 64 + 64 + 64 * 64 + 64          # W3 (64 x 5, input-major), then b3 (5)
+    off_b3 = off_w3 + 64 * 5
+    masked = [o for o, r in enumerate(rel) if not r < threshold]
+    for o in masked:
+        w[off_w3 + o: off_b3: 5] = 0.0
+        w[off_b3 + o] = 0.0
+        nm[24 + o] = 0.0
+    m.set_weights(w)
+    m.set_norm(nm)
+    return masked
+
+
 def held_out_errors(m, X, T):
     """Per-output mean squared error of the network on (X, T) relative to the
     variance of T (1 = no better than predicting the mean, 0 = exact)."""
@@ -119,6 +140,9 @@ def _observe(sim, side):
 
 
 def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0), dt=1e-3, mult=4, every=0.1):
+    """Plain dt, plain mult*dt and learned mult*dt from the same seeded starts.
+    All three observe at the same times: the start of the averaging window and
+    every `every` after it, both rounded to whole macro steps of mult*dt."""
     import torch
     import workloads as wl
     p = wl.Params(L=float(side), zeta=0.02, K=0.02, dt=dt)
@@ -126,39 +150,37 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
     res = {"plain": [], "plain_coarse": [], "learned": []}
     times = {"plain": 0.0, "plain_coarse": 0.0, "learned": 0.0}
     fallbacks = 0
-    n_obs = int(round((t_avg[1] - t_avg[0]) / every)) + 1
+    k_first = max(1, int(round(t_avg[0] / (mult * dt))))        # macro steps to the window
+    k_every = max(1, int(round(every / (mult * dt))))           # macro steps between observations
+    n_obs = int(round((t_avg[1] - t_avg[0]) / (k_every * mult * dt))) + 1
+    spans = [k_first] + [k_every] * (n_obs - 1)
     for s in seeds:
         st = wl.initial_state(side, 1.0, 1.0, seed=3000 + s, kind="isotropic")
         for mode in ("plain", "plain_coarse", "learned"):
             q = p if mode != "plain_coarse" else p.replace(dt=mult * dt)
             sim = _sim([q], [n])
             sim.set_state(0, st)
-            # advance to the start of the averaging window, then observe every `every`
             obs = []
-            t = 0.0
-            targets = [t_avg[0] + k * every for k in range(n_obs)]
-            for tk in targets:
-                span = tk - t
+            for k in spans:
                 torch.cuda.synchronize()
                 c0 = time.perf_counter()
                 if mode == "plain":
-                    sim.step(int(round(span / dt)))
+                    sim.step(k * mult)
                     sim.sync()
                 elif mode == "plain_coarse":
-                    sim.step(int(round(span / (mult * dt))))
+                    sim.step(k)
                     sim.sync()
                 else:
-                    nfb, _ = sim.step_learned(m, int(round(span / (mult * dt))), mult, tau)
+                    nfb, _ = sim.step_learned(m, k, mult, tau)
                     fallbacks += nfb
                 torch.cuda.synchronize()
                 times[mode] += time.perf_counter() - c0
-                t = tk
                 obs.append(_observe(sim, side))
             sim.check()
             sim.close()
             res[mode].append(obs)
             _log(f"evaluated seed {s} {mode}: {times[mode]:.2f} s cumulative")
-    out = {}
+    out = {"window": [k_first * mult * dt, (k_first + k_every * (n_obs - 1)) * mult * dt], "observations": n_obs}
     ref = np.array(res["plain"])           # seeds x times x (ke, defects)
     for mode in res:
         a = np.array(res[mode])
@@ -192,10 +214,14 @@ def main():
     Xh, Th = training_set(replicas=4, mult=args.mult, seed=1)
     rel = held_out_errors(m, Xh, Th)
     _log(f"held-out relative MSE per output (dQxx, dQxy, dQyy, dux, duy): {[round(v, 4) for v in rel]}")
+    masked = mask_unskilled(m, rel)
+    rel_masked = held_out_errors(m, Xh, Th)
+    _log(f"masked outputs {masked}; held-out relative MSE after masking {[round(v, 4) for v in rel_masked]}")
     ev = evaluate(m, tau, side=args.side, seeds=tuple(range(args.seeds)), mult=args.mult)
     t3 = time.perf_counter()
     print(json.dumps({"samples": int(X.shape[0]), "mult": args.mult, "train_loss": loss,
-                      "held_out_rel_mse": rel, "t_samples_s": t1 - t0,
+                      "held_out_rel_mse": rel, "masked_outputs": masked, "held_out_rel_mse_masked": rel_masked,
+                      "t_samples_s": t1 - t0,
                       "t_train_s": t2 - t1, "t_eval_s": t3 - t2, **ev}), flush=True)
 
 

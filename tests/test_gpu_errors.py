@@ -1,0 +1,60 @@
+"""Error paths of the GPU library that the kernels detect themselves: an
+over-full cell (more particles than a cell's staging capacity of 48) is
+reported as NEM_E_OVERFLOW by the step that meets it, and the error is sticky.
+The kernels cap their loops at the capacity, so every access stays in bounds."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import random_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_08919_amd as P
+    P.lib()
+    yield
+
+
+def test_overfull_cell_reports_overflow():
+    import paper_2108_08919_amd as P
+    L = 32                                   # 8 x 8 cells of side 4 (3h + skin = 4.0)
+    p = wl.Params(L=float(L), zeta=0.0, K=0.02)
+    s0 = random_state(L, 5, amp_u=0.0)
+    rng = np.random.default_rng(11)
+    idx = rng.choice(L * L, 60, replace=False)
+    s0["x"][idx] = rng.uniform(8.2, 11.8, 60)   # 60 particles inside the cell [8, 12)^2
+    s0["y"][idx] = rng.uniform(8.2, 11.8, 60)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    sim.step(1)
+    with pytest.raises(P.NemError) as e:
+        sim.check()
+    assert e.value.code == P.NEM_E_OVERFLOW
+    sim.step(1)                              # sticky: still reported
+    with pytest.raises(P.NemError) as e:
+        sim.check()
+    assert e.value.code == P.NEM_E_OVERFLOW
+    sim.close()
+
+
+def test_regular_state_after_overflow_in_another_simulation():
+    """An overflow in one simulation does not leak into a fresh one."""
+    import paper_2108_08919_amd as P
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.01, K=0.02)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, random_state(L, 6))
+    sim.step(3)
+    sim.check()
+    sim.close()

@@ -188,4 +188,13 @@ def test_trained_network_reduces_q_correction_error():
     assert max(rel[:3]) < 0.1
     assert max(rel[3:]) < 1.2
     assert tau > 0
+    # components without held-out skill are switched off and then return exactly zero
+    masked = learned.mask_unskilled(m, rel)
+    assert not set(masked) & {0, 1, 2}
+    Y = m.forward(Xh).cpu().numpy()
+    for o in masked:
+        assert np.all(Y[:, o] == 0.0)
+    rel2 = learned.held_out_errors(m, Xh, Th)
+    for o in range(3):
+        assert rel2[o] == pytest.approx(rel[o], rel=1e-6)
     m.close()
