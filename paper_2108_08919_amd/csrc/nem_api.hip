@@ -73,6 +73,9 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   R.dt = (float)p.dt; R.gamma_eos = (float)p.gamma_eos; R.beta = (float)p.beta;
   R.c0_factor = (float)p.c0_factor; R.mass = (float)(p.rho0 * p.dx * p.dx); R.inv_rho0 = (float)(1.0 / p.rho0);
   R.elastic = p.elastic; R.apd = p.apd;
+  const double delta = 0.1 * p.h;  // Verlet skin
+  R.R2v = (float)((3.0 * p.h + delta) * (3.0 * p.h + delta));
+  R.disp2 = (float)((0.45 * delta) * (0.45 * delta));
   return R;
 }
 
@@ -81,7 +84,7 @@ struct Offs {
   size_t reps, work, cell_start, count, cursor, perm;
   size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id;
   size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell;
-  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe;
+  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe, vl, vcnt, off_build;
   size_t total;
 };
 
@@ -127,6 +130,9 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.ncnt = L.put(sizeof(int) * N);
   o.apdg = L.put(sizeof(float4) * N);
   o.fe = L.put(sizeof(double) * 2 * N);
+  o.vl = L.put(sizeof(uint32_t) * (KMAX / 2) * N);
+  o.vcnt = L.put(sizeof(int) * N);
+  o.off_build = L.put(sizeof(float2) * N);
   o.stage = L.put(sizeof(double) * 9 * (size_t)stage_n);
   o.red = L.put(sizeof(double) * 64 * 1024);
   o.total = L.total + ALIGN;
@@ -162,7 +168,7 @@ SortArgs sort_args(nem_sim* s, const unsigned* gate) {
   a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id;
   a.off = s->off[s->parity]; a.offlo = s->offlo; a.u = s->u; a.q = s->q[s->parity];
   a.drho = s->drho; a.acc = s->acc; a.id = s->id; a.cell = s->cell;
-  a.flags = s->flags; a.gate = gate;
+  a.flags = s->flags; a.gate = gate; a.off_build = s->off_build;
   return a;
 }
 
@@ -178,6 +184,7 @@ StepArgs step_args(nem_sim* s) {
   a.umax_cur = s->umax + (size_t)c * s->R * UMAX_SLOTS; a.umax_nxt = s->umax + (size_t)x * s->R * UMAX_SLOTS;
   a.nl = s->nl; a.ncnt = s->ncnt; a.apdg = s->apdg;
   a.feat = s->feat; a.id = s->id;
+  a.vl = s->vl; a.vcnt = s->vcnt; a.off_build = s->off_build;
   return a;
 }
 
@@ -273,7 +280,8 @@ int enqueue_step(nem_sim* s, hipStream_t st) {
   launch_step_begin(s->flags, a.umax_nxt, s->R, st);
   for (int pass = 1; pass <= 4; ++pass) {
     Timed t(s, pass);
-    if (!launch_pass(pass, cfg, a, st)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
+    const bool ok = pass == 1 ? launch_pass_a_verlet(cfg, a, st) : launch_pass(pass, cfg, a, st);
+    if (!ok) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
   }
   HIPCHK(hipGetLastError());
   return NEM_OK;
@@ -460,6 +468,7 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   s->stage = (double*)(b + o.stage); s->red = (double*)(b + o.red);
   s->nl = (uint32_t*)(b + o.nl); s->ncnt = (int*)(b + o.ncnt); s->apdg = (float4*)(b + o.apdg);
   s->fe = (double*)(b + o.fe);
+  s->vl = (uint32_t*)(b + o.vl); s->vcnt = (int*)(b + o.vcnt); s->off_build = (float2*)(b + o.off_build);
 
   int cell_base = 0, part_base = 0;
   for (int r = 0; r < R; ++r) {
@@ -497,6 +506,7 @@ int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const
   SortArgs a = sort_args(s, nullptr);
   launch_ingest(a, r, s->stage, n, s->umax + (size_t)s->parity * s->R * UMAX_SLOTS, s->stream);
   launch_sort_tail(a, R.part_base, n, R.cell_base, R.nc * R.nc, R.part_base, s->stream);
+  launch_request_relist(s->flags, s->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s->stream));
   s->has_state[r] = 1;
@@ -689,6 +699,7 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
       if (value != 4 && value != 8) return NEM_E_INVAL;
       drop_graphs(s);
       s->T = (int)value;
+      launch_request_relist(s->flags, s->stream);  // LDS slots of the Verlet list change with the tile
       return build_work(s);
     }
     case NEM_OPT_LPP:

@@ -38,7 +38,9 @@ struct RepDev {
   float lam, A, C, K;
   float zeta, dt, gamma_eos, beta;
   float c0_factor, mass, inv_rho0, B;
-  int elastic, apd, pad0, pad1;
+  int elastic, apd;
+  float R2v;       // Verlet list radius: fl32((3h + delta)^2), delta = 0.1 h
+  float disp2;     // rebuild the Verlet list when a particle moved more than 0.45 delta: (0.45 delta)^2
   double csd, Ld;
 };
 
@@ -68,14 +70,17 @@ struct StepArgs {
   float2* pi;             // lambda part of the elastic stress (Pi_xx, Pi_xy)
   float* P;               // p / rho_hat^2
   float* drhat;           // rho_hat - rho0
-  unsigned* flags;        // [0] error bits, [1] rebin request
+  unsigned* flags;        // [0] error bits, [1] rebin request, [2] Verlet rebuild request, [3] rebuild this step
   const unsigned* umax_cur;  // [R][UMAX_SLOTS]: max |u^{n+1/2}| (float bits)
   unsigned* umax_nxt;        // [R][UMAX_SLOTS]: max |u^{n+3/2}| being accumulated
   uint32_t* nl;              // neighbour list: word w of particle g at nl[w*ntot + g],
                              // two 16-bit entries (LDS slot | (dx+1)<<12 | (dy+1)<<14)
   int* ncnt;                 // accepted neighbours per particle
   float4* apdg;              // APD geometry: (sum rx/r^3, sum ry/r^3, sum r, count)
-  float* feat;               // NULL, or 12 features per particle at [part_base + id]
+  float* feat;               // NULL, or 12 features per particle at [g] (storage order)
+  uint32_t* vl;              // Verlet list (pairs within the Verlet radius), layout as nl
+  int* vcnt;                 // Verlet list length
+  float2* off_build;         // offset of each particle when the Verlet list was built
   const int* id;             // particle ids (sorted order)
 };
 
@@ -97,10 +102,13 @@ struct SortArgs {
   float2* off; float2* offlo; float2* u; float2* q; float* drho; float2* acc; int* id; int* cell;
   unsigned* flags;
   const unsigned* gate;  // run only when *gate != 0 (NULL: always)
+  const float2* off_build;  // offsets at the last Verlet build (displacement checks)
 };
 
 // Launchers (nem_passes.hip, nem_sort.hip).
 bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s);
+bool launch_pass_a_verlet(const PassCfg& c, const StepArgs& a, hipStream_t s);
+void launch_request_relist(unsigned* flags, hipStream_t st);
 void launch_neighbors(int T, const StepArgs& a, const int* sid, int rep, int mode, int* cnt,
                       const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s);
 void launch_ingest(const SortArgs& s, int r, const double* in, int n, unsigned* umax, hipStream_t st);

@@ -44,17 +44,30 @@ __device__ inline int rep_of(const RepDev* reps, int R, int k) {
 }
 
 // Max of v over the workgroup (all threads call it; v >= 0), then one atomic
-// into this workgroup's max-speed slot of replica r.
-__device__ __forceinline__ void block_speed_max(unsigned* umax_cur, int r, float v) {
+// into this workgroup's max-speed slot of replica r; any thread's relist
+// request becomes one atomic on the Verlet rebuild flag.
+__device__ __forceinline__ void block_speed_max(const SortArgs& s, unsigned* umax_cur, int r, float v, bool relist) {
   __shared__ float red[4];
+  __shared__ int any_relist;
+  if (threadIdx.x == 0) any_relist = 0;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
+  if (relist) any_relist = 1;
+  __syncthreads();
   if (threadIdx.x == 0) {
     const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
     if (m > 0.0f) atomicMax(&umax_cur[r * UMAX_SLOTS + (blockIdx.x & (UMAX_SLOTS - 1))], __float_as_uint(m));
+    if (any_relist) atomicOr(&s.flags[2], 1u);
   }
+}
+
+// Offset moved further from its value at the last Verlet build than allowed.
+__device__ __forceinline__ bool moved_too_far(const SortArgs& s, const RepDev& R, int k, float2 nh) {
+  const float2 ob = s.off_build[k];
+  const float bx = nh.x - ob.x, by = nh.y - ob.y;
+  return bx * bx + by * by > R.disp2;
 }
 
 // Change every replica's time step by `factor`: recover r^n, u^n from the
@@ -67,6 +80,7 @@ __global__ __launch_bounds__(256) void k_repredict(SortArgs s, float factor, uns
   const RepDev& R = s.reps[r];
   const float dto = R.dt, dtn = dto * factor;
   float vmax = 0.0f;
+  bool relist = false;
   for (int k = R.part_base + blockIdx.x * blockDim.x + threadIdx.x; k < R.part_base + R.n;
        k += gridDim.x * blockDim.x) {
     const float2 u = s.u[k], ac = s.acc[k], o = s.off[k], lo = s.offlo[k];
@@ -85,8 +99,9 @@ __global__ __launch_bounds__(256) void k_repredict(SortArgs s, float factor, uns
     s.offlo[k] = nl;
     s.u[k] = make_float2(unx, uny);
     vmax = fmaxf(vmax, sqrtf(unx * unx + uny * uny));
+    relist |= moved_too_far(s, R, k, nh);
   }
-  block_speed_max(umax_cur, r, vmax);
+  block_speed_max(s, umax_cur, r, vmax, relist);
 }
 
 // (Qxx, Qxy, Qyy, ux, uy) at the integer level into out[(part_base + id) * 5].
@@ -116,6 +131,7 @@ __global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, uns
   const int r = blockIdx.y;
   const RepDev& R = s.reps[r];
   float vmax = 0.0f;
+  bool relist = false;
   for (int k = R.part_base + blockIdx.x * blockDim.x + threadIdx.x; k < R.part_base + R.n;
        k += gridDim.x * blockDim.x) {
     const float* y = Y + (size_t)k * 5;
@@ -140,8 +156,9 @@ __global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, uns
     s.off[k] = nh;
     s.offlo[k] = nl;
     vmax = fmaxf(vmax, sqrtf(u.x * u.x + u.y * u.y));
+    relist |= moved_too_far(s, R, k, nh);
   }
-  block_speed_max(umax_cur, r, vmax);
+  block_speed_max(s, umax_cur, r, vmax, relist);
 }
 
 // dst[(part_base + id) * w + c] = src[k * w + c]: rows from storage order to
@@ -255,8 +272,10 @@ int restore_snapshot(nem_sim* s) {
   HIPCHK(hipMemcpyAsync(s->cell_start, S.cell_start, sizeof(int) * (C + 1), d2d, s->stream));
   HIPCHK(hipMemcpyAsync(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
                         s->stream));
-  // keep the sticky error bits (flags[0]), restore the rebin request (flags[1])
+  // keep the sticky error bits (flags[0]), restore the rebin request (flags[1]);
+  // the Verlet list is not part of the snapshot: rebuild it
   HIPCHK(hipMemcpyAsync(s->flags + 1, S.umax + s->R * UMAX_SLOTS, sizeof(unsigned), d2d, s->stream));
+  launch_request_relist(s->flags, s->stream);
   s->parity = p;
   for (int r = 0; r < s->R; ++r) s->reps[r].dt = S.dt[r];
   int rc = upload_reps(s);

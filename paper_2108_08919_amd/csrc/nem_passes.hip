@@ -181,6 +181,179 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
   }
 }
 
+// ------------------------------------------------------------- pass A, Verlet
+// Between builds of the Verlet list (every pair of the 3 x 3 stencil closer
+// than 3h + delta, delta = 0.1 h), pass A walks that list instead of the ~144
+// candidates: each listed pair is put through the exact predicate again and the
+// accepted ones make the step's neighbour list, sums and counts, exactly as
+// the candidate search would. The list stays a superset while no particle has
+// moved more than 0.45 delta since the build (pass D checks and requests a
+// rebuild, as does every rebin, new state, tile change or snapshot restore):
+// a pair left out was at least 3h + delta apart, so it is still more than
+// 3h + 0.1 delta apart; pairs outside the stencil are excluded by the rebin
+// criterion as before.
+
+// The step's neighbour list of one particle under construction: accepted pairs
+// are summed (V, APD geometry) and appended as 16-bit entries.
+template <int COMP>
+struct ExactSink {
+  Acc<COMP> sw, sx3, sy3, sr;
+  int kept;
+  uint32_t word;
+  uint32_t* dst;
+  int64_t ntot;
+  __device__ __forceinline__ void init(const StepArgs& a, int g) {
+    sw.init(); sx3.init(); sy3.init(); sr.init();
+    kept = 0; word = 0u; dst = a.nl + g; ntot = a.ntot;
+  }
+  __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
+    float rinv, r;
+    sw.add(quintic_Wr(R, r2, rinv, r));
+    const float r3 = rinv * rinv * rinv;
+    sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
+    if (kept < KMAX) {
+      if (kept & 1) dst[(size_t)(kept >> 1) * ntot] = word | (e << 16);
+      else word = e;
+    }
+    ++kept;
+    if ((kept & 15) == 0) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
+  }
+  __device__ __forceinline__ void finish(const StepArgs& a, const RepDev& R, int g) {
+    const int nk = min(kept, KMAX);
+    if (nk & 1) dst[(size_t)(nk >> 1) * ntot] = word;
+    sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
+    if (kept > KMAX) flag(a.flags, ERR_OVERFLOW);
+    a.V[g] = 1.0f / (R.W0 + sw.value());
+    a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)nk);
+    a.ncnt[g] = nk;
+  }
+};
+
+// Build: candidate search with the Verlet radius (masks as in pass A), then one
+// walk over the Verlet pairs in cell order that writes the Verlet list and
+// feeds the pairs passing the exact predicate to the step's list.
+template <int T, int COMP>
+__device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
+  __shared__ TileLDS<T> L;
+  __shared__ float2 s_off[TileCfg<T>::MAXP];
+  __shared__ unsigned long long s_mask[9 * WG];
+  RepDev R;
+  int rep;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
+  const int S = L.cstart[nreg];
+  for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
+  __syncthreads();
+  const int nin = L.cstart[nint];
+  const int tid = threadIdx.x;
+  for (int base = 0; base < nin; base += WG) {
+    const int p = base + tid;
+    if (p >= nin) break;
+    const int st = find_cell(L.cstart, nint, p);
+    const int li = st % ni, lj = st / ni;
+    const float2 oi = s_off[p];
+    int cnt = 0;
+    bool big = false;
+#pragma unroll 1
+    for (int cidx = 0; cidx < 9; ++cidx) {
+      const int dy = cidx / 3, dx = cidx % 3;
+      const int sc = L.slot[(lj + dy) * (ni + 2) + (li + dx)];
+      const int j0 = L.cstart[sc];
+      const int nj = L.cstart[sc + 1] - j0;
+      if (nj > CELL_MAX) big = true;
+      const uint32_t code = (uint32_t)dx | ((uint32_t)dy << 2);
+      const float2 sh = L.shift[code];
+      uint32_t mlo = 0u, mhi = 0u;
+      const int n0 = min(nj, 32), n1 = min(nj, CELL_MAX);
+      for (int b = 0; b < n0; ++b) {
+        const float2 oj = s_off[j0 + b];
+        float rx, ry, r2;
+        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2v, rx, ry, r2)) mlo |= 1u << b;
+      }
+      for (int b = 32; b < n1; ++b) {
+        const float2 oj = s_off[j0 + b];
+        float rx, ry, r2;
+        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2v, rx, ry, r2)) mhi |= 1u << (b - 32);
+      }
+      s_mask[cidx * WG + tid] = ((unsigned long long)code << 60) | ((unsigned long long)j0 << 48) |
+                                ((unsigned long long)mhi << 32) | mlo;
+      cnt += __popc(mlo) + __popc(mhi);
+    }
+    const int vk = min(cnt, KMAX);
+    const int g = L.gstart[st] + (p - L.cstart[st]);
+    if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
+    if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
+    ExactSink<COMP> out;
+    out.init(a, g);
+    int c = -1;
+    unsigned long long m = 0ull, x = 0ull;
+    uint32_t vword = 0u;
+    uint32_t* vdst = a.vl + g;
+    for (int k = 0; k < vk; ++k) {
+      while (m == 0ull && c < 8) {
+        ++c;
+        x = s_mask[c * WG + tid];
+        m = x & MASK48;
+      }
+      const uint32_t hi = (uint32_t)(x >> 48);
+      const int j = (int)(hi & 0xFFFu) + __builtin_ctzll(m);
+      m &= m - 1ull;
+      const uint32_t e = (uint32_t)j | (hi & 0xF000u);
+      if (k & 1) vdst[(size_t)(k >> 1) * a.ntot] = vword | (e << 16);
+      else vword = e;
+      const float2 sh = L.shift[hi >> 12];
+      const float2 oj = s_off[j];
+      float rx, ry, r2;
+      if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) out.take(R, e, rx, ry, r2);
+    }
+    if (vk & 1) vdst[(size_t)(vk >> 1) * a.ntot] = vword;
+    a.vcnt[g] = vk;
+    a.off_build[g] = oi;
+    out.finish(a, R, g);
+  }
+}
+
+// Walk: the Verlet pairs of each particle through the exact predicate.
+template <int T, int COMP>
+__device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
+  __shared__ TileLDS<T> L;
+  __shared__ float2 s_off[TileCfg<T>::MAXP];
+  RepDev R;
+  int rep;
+  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  const int nint = L.hdr[2], nreg = L.hdr[3];
+  const int S = L.cstart[nreg];
+  for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
+  __syncthreads();
+  const int nin = L.cstart[nint];
+  for (int base = 0; base < nin; base += WG) {
+    const int p = base + threadIdx.x;
+    if (p >= nin) break;
+    const int st = find_cell(L.cstart, nint, p);
+    const int g = L.gstart[st] + (p - L.cstart[st]);
+    if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
+    const float2 oi = s_off[p];
+    const int vk = min(a.vcnt[g], KMAX);
+    ExactSink<COMP> out;
+    out.init(a, g);
+    const uint32_t* src = a.vl + g;
+    for (int k = 0; k < vk; k += 2) {
+      const uint32_t wd = src[(size_t)(k >> 1) * a.ntot];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (k + h >= vk) break;
+        const uint32_t e = h ? (wd >> 16) : (wd & 0xFFFFu);
+        const int j = min((int)(e & 0xFFFu), S - 1);
+        const float2 sh = L.shift[(e >> 12) & 15u];
+        const float2 oj = s_off[j];
+        float rx, ry, r2;
+        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) out.take(R, e, rx, ry, r2);
+      }
+    }
+    out.finish(a, R, g);
+  }
+}
+
 // ------------------------------------------------------------------ pass B
 template <int T, int COMP, int FORM, int EL>
 __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
@@ -450,7 +623,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __syncthreads();
   const int nin = L.cstart[nint];
   float umax_l = 0.0f;
-  bool rebin = false, bad = false;
+  bool rebin = false, bad = false, relist = false;
   for (int base = 0; base < nin;) {
     const int lpp = lanes_for(nin - base, a.lpp);
     const int p = base + threadIdx.x / lpp;
@@ -543,6 +716,9 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
         nh.y = s + l2; nl.y = l2 - (nh.y - s);
       }
       const float dn = drh + hdt * bk.w;
+      const float2 ob = a.off_build[g];
+      const float bx = nh.x - ob.x, by = nh.y - ob.y;
+      if (bx * bx + by * by > R.disp2) relist = true;
       a.off_nxt[g] = nh;
       a.offlo[g] = nl;
       a.u[g] = make_float2(unx, uny);
@@ -565,6 +741,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
     if (m > 0.0f) atomicMax(&a.umax_nxt[rep * UMAX_SLOTS + (w & (UMAX_SLOTS - 1))], __float_as_uint(m));
   }
   if (rebin) atomicOr(&a.flags[1], 1u);
+  if (relist) atomicOr(&a.flags[2], 1u);
   if (bad) flag(a.flags, ERR_NUMERIC);
 }
 
@@ -707,6 +884,19 @@ template <int T, int COMP>
 __global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a<T, COMP>(a, w); __syncthreads(); }
 }
+// Gated on the rebuild flag of this step (flags[3], set by the step-begin
+// kernel): exactly one of the two runs its tiles, the other exits at once.
+template <int T, int COMP>
+__global__ __launch_bounds__(WG) void k_pass_a_build(const StepArgs a) {
+  if (a.flags[3] == 0u) return;
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_build<T, COMP>(a, w); __syncthreads(); }
+}
+template <int T, int COMP>
+__global__ __launch_bounds__(WG) void k_pass_a_walk(const StepArgs a) {
+  if (a.flags[3] != 0u) return;
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_walk<T, COMP>(a, w); __syncthreads(); }
+}
+
 template <int T, int COMP, int FORM, int EL>
 __global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL>(a, w); __syncthreads(); }
@@ -746,6 +936,28 @@ static bool launch_comp(int pass, const PassCfg& c, const StepArgs& a, hipStream
     case 0: return launch_phys<T, 0>(pass, c, a, s);
     case 1: return launch_phys<T, 1>(pass, c, a, s);
     case 2: return launch_phys<T, 2>(pass, c, a, s);
+  }
+  return false;
+}
+
+template <int T, int COMP>
+static void launch_verlet(const StepArgs& a, hipStream_t s) {
+  const int full = a.grid > 0 ? std::min(a.grid, a.nwork) : a.nwork;
+  // the build runs rarely: a persistent grid keeps the skipped launch short
+  hipLaunchKernelGGL((k_pass_a_build<T, COMP>), dim3(std::min(full, 2048)), dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_pass_a_walk<T, COMP>), dim3(full), dim3(WG), 0, s, a);
+}
+
+// Pass A of a step: Verlet build (when flagged) or walk.
+bool launch_pass_a_verlet(const PassCfg& c, const StepArgs& a, hipStream_t s) {
+  if (c.T != 4 && c.T != 8) return false;
+  switch (c.COMP * 2 + (c.T == 8 ? 1 : 0)) {
+    case 0: launch_verlet<4, 0>(a, s); return true;
+    case 1: launch_verlet<8, 0>(a, s); return true;
+    case 2: launch_verlet<4, 1>(a, s); return true;
+    case 3: launch_verlet<8, 1>(a, s); return true;
+    case 4: launch_verlet<4, 2>(a, s); return true;
+    case 5: launch_verlet<8, 2>(a, s); return true;
   }
   return false;
 }

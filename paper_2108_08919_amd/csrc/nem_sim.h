@@ -32,6 +32,7 @@ struct nem_sim {
   float* uv = nullptr; float2* pi = nullptr; float* P = nullptr; float* drhat = nullptr;
   unsigned* flags = nullptr; unsigned* umax = nullptr;
   uint32_t* nl = nullptr; int* ncnt = nullptr; float4* apdg = nullptr; double* fe = nullptr;
+  uint32_t* vl = nullptr; int* vcnt = nullptr; float2* off_build = nullptr;  // Verlet list
   double* stage = nullptr; int64_t stage_n = 0;
   double* red = nullptr;
   int parity = 0;

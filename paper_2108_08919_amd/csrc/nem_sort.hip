@@ -201,10 +201,22 @@ __global__ void k_gather(SortArgs s, int k0, int n, int c0, int nc) {
 
 // Start of a step: clear the rebin request (after the gated kernels read it)
 // and the next step's max-speed accumulators.
+// After the (gated) rebin: decide whether this step rebuilds the Verlet list
+// (a rebin happened or a rebuild was requested), clear both requests, and clear
+// the max-speed slots that this step's pass D fills.
 __global__ void k_step_begin(unsigned* flags, unsigned* umax_nxt, int R) {
   const int t = threadIdx.x;
-  if (t == 0) flags[1] = 0u;
+  if (t == 0) {
+    flags[3] = (flags[1] | flags[2]) ? 1u : 0u;
+    flags[2] = 0u;
+    flags[1] = 0u;
+  }
   for (int r = t; r < R * UMAX_SLOTS; r += blockDim.x) umax_nxt[r] = 0u;
+}
+
+// Request a Verlet rebuild at the next step (new state, tile change, restore).
+__global__ void k_request_relist(unsigned* flags) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[2] = 1u;
 }
 
 // Sorted state of replica r -> FP64 arrays in id order at the integer time
@@ -311,6 +323,9 @@ void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base
 }
 void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st) {
   hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, st, flags, umax_nxt, R);
+}
+void launch_request_relist(unsigned* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_request_relist, dim3(1), dim3(64), 0, st, flags);
 }
 void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st) {
   hipLaunchKernelGGL(k_int_offsets, dim3(grid_for(s.ntot)), dim3(256), 0, st, s, out);
