@@ -897,8 +897,18 @@ __global__ __launch_bounds__(WG) void k_pass_a_walk(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_walk<T, COMP>(a, w); __syncthreads(); }
 }
 
+// Occupancy targets (waves per SIMD) of the pair passes: more resident waves
+// hide the LDS and list latency in each pair's dependency chain; the targets
+// are the largest that compile without register spills for the variant.
 template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) void k_pass_b(const StepArgs a) {
+struct Waves {
+  static constexpr int B = (T == 4 && (COMP == 0 || (COMP == 1 && FORM == 0))) ? 5 : 1;
+  static constexpr int D = (T == 4 && EL == 0) ? 8 : 1;
+};
+
+template <int T, int COMP, int FORM, int EL>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL>::B)))
+void k_pass_b(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL>(a, w); __syncthreads(); }
 }
 template <int T, int COMP>
@@ -906,7 +916,8 @@ __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP>(a, w); __syncthreads(); }
 }
 template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) void k_pass_d(const StepArgs a) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL>::D)))
+void k_pass_d(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL>(a, w); __syncthreads(); }
 }
 
