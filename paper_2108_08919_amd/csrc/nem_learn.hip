@@ -175,6 +175,27 @@ __global__ void k_rows_by_id(SortArgs s, const float* src, float* dst, int w) {
   }
 }
 
+// Device-to-device copy of up to 12 buffers in one launch (16-byte chunks,
+// then 4-byte words for the tail; every buffer is 4-byte sized and every
+// buffer longer than 16 bytes starts 16-byte aligned).
+struct CopySeg { const void* src; void* dst; int64_t bytes; };
+struct CopyList { CopySeg seg[12]; int n; };
+__global__ void k_copy_list(CopyList L) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < L.n; ++k) {
+    const CopySeg sg = L.seg[k];
+    const int64_t n16 = sg.bytes / 16;
+    const uint4* s16 = (const uint4*)sg.src;
+    uint4* d16 = (uint4*)sg.dst;
+    for (int64_t i = t0; i < n16; i += stride) d16[i] = s16[i];
+    const int64_t n4 = (sg.bytes - n16 * 16) / 4;
+    const uint32_t* s4 = (const uint32_t*)((const char*)sg.src + n16 * 16);
+    uint32_t* d4 = (uint32_t*)((char*)sg.dst + n16 * 16);
+    for (int64_t i = t0; i < n4; i += stride) d4[i] = s4[i];
+  }
+}
+
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
 
 // (chunks, replicas) grid for the per-replica kernels.
@@ -235,19 +256,22 @@ int take_snapshot(nem_sim* s) {
     S.alloc = true;
   }
   const int p = s->parity;
-  const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
-  HIPCHK(hipMemcpyAsync(S.off, s->off[p], sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.offlo, s->offlo, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.u, s->u, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.q, s->q[p], sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.acc, s->acc, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.drho, s->drho, sizeof(float) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.id, s->id, sizeof(int) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.cell, s->cell, sizeof(int) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.cell_start, s->cell_start, sizeof(int) * (C + 1), d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(S.umax, s->umax + (size_t)p * s->R * UMAX_SLOTS, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
-                        s->stream));
-  HIPCHK(hipMemcpyAsync(S.umax + s->R * UMAX_SLOTS, s->flags + 1, sizeof(unsigned), d2d, s->stream));
+  CopyList cl;
+  cl.n = 0;
+  auto add = [&](const void* src, void* dst, size_t bytes) { cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes}; };
+  add(s->off[p], S.off, sizeof(float2) * N);
+  add(s->offlo, S.offlo, sizeof(float2) * N);
+  add(s->u, S.u, sizeof(float2) * N);
+  add(s->q[p], S.q, sizeof(float2) * N);
+  add(s->acc, S.acc, sizeof(float2) * N);
+  add(s->drho, S.drho, sizeof(float) * N);
+  add(s->id, S.id, sizeof(int) * N);
+  add(s->cell, S.cell, sizeof(int) * N);
+  add(s->cell_start, S.cell_start, sizeof(int) * (C + 1));
+  add(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS);
+  add(s->flags + 1, S.umax + s->R * UMAX_SLOTS, sizeof(unsigned));  // rebin request
+  hipLaunchKernelGGL(k_copy_list, dim3(1024), dim3(256), 0, s->stream, cl);
+  HIPCHK(hipGetLastError());
   S.parity = p;
   S.dt.resize(s->R);
   for (int r = 0; r < s->R; ++r) S.dt[r] = s->reps[r].dt;
@@ -260,21 +284,24 @@ int restore_snapshot(nem_sim* s) {
   if (!S.valid) return NEM_E_STATE;
   const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
   const int p = S.parity;
-  const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
-  HIPCHK(hipMemcpyAsync(s->off[p], S.off, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->offlo, S.offlo, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->u, S.u, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->q[p], S.q, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->acc, S.acc, sizeof(float2) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->drho, S.drho, sizeof(float) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->id, S.id, sizeof(int) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->cell, S.cell, sizeof(int) * N, d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->cell_start, S.cell_start, sizeof(int) * (C + 1), d2d, s->stream));
-  HIPCHK(hipMemcpyAsync(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS, d2d,
-                        s->stream));
+  CopyList cl;
+  cl.n = 0;
+  auto add = [&](const void* src, void* dst, size_t bytes) { cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes}; };
+  add(S.off, s->off[p], sizeof(float2) * N);
+  add(S.offlo, s->offlo, sizeof(float2) * N);
+  add(S.u, s->u, sizeof(float2) * N);
+  add(S.q, s->q[p], sizeof(float2) * N);
+  add(S.acc, s->acc, sizeof(float2) * N);
+  add(S.drho, s->drho, sizeof(float) * N);
+  add(S.id, s->id, sizeof(int) * N);
+  add(S.cell, s->cell, sizeof(int) * N);
+  add(S.cell_start, s->cell_start, sizeof(int) * (C + 1));
+  add(S.umax, s->umax + (size_t)p * s->R * UMAX_SLOTS, sizeof(unsigned) * s->R * UMAX_SLOTS);
   // keep the sticky error bits (flags[0]), restore the rebin request (flags[1]);
   // the Verlet list is not part of the snapshot: rebuild it
-  HIPCHK(hipMemcpyAsync(s->flags + 1, S.umax + s->R * UMAX_SLOTS, sizeof(unsigned), d2d, s->stream));
+  add(S.umax + s->R * UMAX_SLOTS, s->flags + 1, sizeof(unsigned));
+  hipLaunchKernelGGL(k_copy_list, dim3(1024), dim3(256), 0, s->stream, cl);
+  HIPCHK(hipGetLastError());
   launch_request_relist(s->flags, s->stream);
   s->parity = p;
   for (int r = 0; r < s->R; ++r) s->reps[r].dt = S.dt[r];

@@ -182,6 +182,7 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P, MlpNorm nm,
                                                      const float* __restrict__ X, int64_t n, float* Y,
                                                      unsigned* maxnorm) {
+  constexpr int NB = 2;  // independent 16-sample blocks per iteration (instruction-level parallelism)
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, g = l >> 4, c = l & 15;
   // this lane's input features 8g + i (i < nf) and their normalisation
   const int nf = g == 0 ? 8 : (g == 1 ? NI - 8 : 0);
@@ -191,8 +192,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
     xm8[i] = i < nf ? nm.xm[8 * g + i] : 0.0f;
     xr8[i] = i < nf ? nm.xr[8 * g + i] : 0.0f;
   }
+  // weights as A fragments; biases as the accumulators' initial values
   bf16x8 a1[4], a2[4][2], a3[2];
-  float bb1[4][4], bb2[4][4], bb3[4];
+  f32x4 b1[4], b2[4], b3;
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
       for (int i = 0; i < 8; ++i) a2[mt][kc][i] = (bf16)P[OFF_W2 + unit_of(kc, g, i) * NH + 16 * mt + c];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      bb1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
-      bb2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
+      b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
+      b2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
     }
   }
 #pragma unroll
@@ -215,71 +217,81 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
 #pragma unroll
     for (int i = 0; i < 8; ++i) a3[kc][i] = (bf16)(c < NO ? P[OFF_W3 + unit_of(kc, g, i) * NO + c] : 0.0f);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) bb3[i] = (4 * g + i < NO) ? P[OFF_B3 + 4 * g + i] : 0.0f;
+  for (int i = 0; i < 4; ++i) b3[i] = (4 * g + i < NO) ? P[OFF_B3 + 4 * g + i] : 0.0f;
 
   float mx = 0.0f;
   const int64_t nblk = (n + 15) / 16;
-  for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nblk; b += (int64_t)gridDim.x * 4) {
-    const int64_t s = b * 16 + c;
-    const float* xrow = X + (s < n ? s : n - 1) * NI + 8 * g;  // clamped: in bounds for every lane
-    float xv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (VEC) {
-      if (nf > 0) {
-        const float4 v0 = *reinterpret_cast<const float4*>(xrow);
-        xv[0] = v0.x; xv[1] = v0.y; xv[2] = v0.z; xv[3] = v0.w;
+  for (int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) * NB; b0 < nblk; b0 += (int64_t)gridDim.x * 4 * NB) {
+    int64_t s[NB];
+    bf16x8 xb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      s[q] = (b0 + q) * 16 + c;
+      const float* xrow = X + (s[q] < n ? s[q] : n - 1) * NI + 8 * g;  // clamped: in bounds for every lane
+      float xv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (VEC) {
+        if (nf > 0) {
+          const float4 v0 = *reinterpret_cast<const float4*>(xrow);
+          xv[0] = v0.x; xv[1] = v0.y; xv[2] = v0.z; xv[3] = v0.w;
+        }
+        if (nf > 4) {
+          const float4 v1 = *reinterpret_cast<const float4*>(xrow + 4);
+          xv[4] = v1.x; xv[5] = v1.y; xv[6] = v1.z; xv[7] = v1.w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < nf) xv[i] = xrow[i];
       }
-      if (nf > 4) {
-        const float4 v1 = *reinterpret_cast<const float4*>(xrow + 4);
-        xv[4] = v1.x; xv[5] = v1.y; xv[6] = v1.z; xv[7] = v1.w;
+      const float keep = s[q] < n ? 1.0f : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xb[q][i] = (bf16)(keep * ((xv[i] - xm8[i]) * xr8[i]));
+    }
+    f32x4 d[NB][4];
+    bf16x8 hb[NB][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a1[mt], xb[q], b1[mt]);
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[q][kc][i] = (bf16)fast_tanh(d[q][2 * kc][i]);
+          hb[q][kc][4 + i] = (bf16)fast_tanh(d[q][2 * kc + 1][i]);
+        }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a2[mt][1], hb[q][1], mfma(a2[mt][0], hb[q][0], b2[mt]));
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[q][kc][i] = (bf16)fast_tanh(d[q][2 * kc][i]);
+          hb[q][kc][4 + i] = (bf16)fast_tanh(d[q][2 * kc + 1][i]);
+        }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const f32x4 y = mfma(a3[1], hb[q][1], mfma(a3[0], hb[q][0], b3));
+      // lane (g, c) holds outputs 4g + i of sample s: g = 0 -> 0..3, g = 1 -> 4
+      float sq = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int o = 4 * g + i;
+        if (o < NO) {
+          sq += y[i] * y[i];
+          if (s[q] < n) Y[s[q] * NO + o] = y[i] * nm.ys[o] + nm.ym[o];
+        }
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < nf) xv[i] = xrow[i];
+      sq += __shfl_xor(sq, 16, 64);
+      sq += __shfl_xor(sq, 32, 64);
+      if (s[q] < n) mx = fmaxf(mx, sqrtf(sq));
     }
-    const float keep = s < n ? 1.0f : 0.0f;
-    bf16x8 xb;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) xb[i] = (bf16)(keep * ((xv[i] - xm8[i]) * xr8[i]));
-    f32x4 d1[4], d2[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      d1[mt] = mfma(a1[mt], xb, f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-      for (int i = 0; i < 4; ++i) d1[mt][i] = fast_tanh(d1[mt][i] + bb1[mt][i]);
-    }
-    bf16x8 hb[2];
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) { hb[kc][i] = (bf16)d1[2 * kc][i]; hb[kc][4 + i] = (bf16)d1[2 * kc + 1][i]; }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      d2[mt] = mfma(a2[mt][0], hb[0], f32x4{0.f, 0.f, 0.f, 0.f});
-      d2[mt] = mfma(a2[mt][1], hb[1], d2[mt]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) d2[mt][i] = fast_tanh(d2[mt][i] + bb2[mt][i]);
-    }
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) { hb[kc][i] = (bf16)d2[2 * kc][i]; hb[kc][4 + i] = (bf16)d2[2 * kc + 1][i]; }
-    f32x4 y = mfma(a3[0], hb[0], f32x4{0.f, 0.f, 0.f, 0.f});
-    y = mfma(a3[1], hb[1], y);
-    // lane (g, c) holds outputs 4g + i of sample s: g = 0 -> 0..3, g = 1 -> 4
-    float sq = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int o = 4 * g + i;
-      y[i] += bb3[i];
-      if (o < NO) {
-        sq += y[i] * y[i];
-        if (s < n) Y[s * NO + o] = y[i] * nm.ys[o] + nm.ym[o];
-      }
-    }
-    sq += __shfl_xor(sq, 16, 64);
-    sq += __shfl_xor(sq, 32, 64);
-    if (s < n) mx = fmaxf(mx, sqrtf(sq));
   }
   if (maxnorm) {
 #pragma unroll
@@ -505,7 +517,7 @@ void launch_mlp_forward(const float* P, const float* norm, const float* X, int64
   MlpNorm nm;
   for (int i = 0; i < NI; ++i) { nm.xm[i] = norm[i]; nm.xs[i] = norm[NI + i]; nm.xr[i] = 1.0f / norm[NI + i]; }
   for (int i = 0; i < NO; ++i) { nm.ym[i] = norm[2 * NI + i]; nm.ys[i] = norm[2 * NI + NO + i]; }
-  const int64_t nblk = (n + 15) / 16;
+  const int64_t nblk = (n + 31) / 32;  // pairs of 16-sample blocks
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nblk + 3) / 4, 1024));
   if (((uintptr_t)X & 15u) == 0)
     hipLaunchKernelGGL(k_mlp_forward<true>, dim3(grid), dim3(256), 0, s, P, nm, X, n, Y, maxnorm);
