@@ -126,8 +126,12 @@ __global__ void k_sub(float* T, const float* C, int64_t n) {
 
 // Add the network's corrections Y[k * 5] (storage order) to Q (projected on
 // traceless tensors) and u; refill the max-speed slots (cleared by the
-// caller). Grid as k_repredict.
-__global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, unsigned* umax_cur) {
+// caller). Grid as k_repredict. Skipped when the largest predicted correction
+// norm (maxnorm, float bits) exceeds tau (bits of a positive float, so the
+// unsigned comparison orders them as floats).
+__global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, unsigned* umax_cur,
+                                                 const unsigned* maxnorm, unsigned tau_bits) {
+  if (maxnorm && *maxnorm > tau_bits) return;  // the macro step will be replayed as fine steps
   const int r = blockIdx.y;
   const RepDev& R = s.reps[r];
   float vmax = 0.0f;
@@ -232,15 +236,16 @@ struct nem_mlp {
 namespace nem_host {
 
 void free_snapshot(nem_sim* s) {
-  auto& S = s->snap;
-  for (void* p : {(void*)S.off, (void*)S.offlo, (void*)S.u, (void*)S.q, (void*)S.acc, (void*)S.drho, (void*)S.id,
-                  (void*)S.cell, (void*)S.cell_start, (void*)S.umax})
-    if (p) hipFree(p);
-  S = nem_sim::Snap();
+  for (auto& S : s->snap) {
+    for (void* p : {(void*)S.off, (void*)S.offlo, (void*)S.u, (void*)S.q, (void*)S.acc, (void*)S.drho, (void*)S.id,
+                    (void*)S.cell, (void*)S.cell_start, (void*)S.umax})
+      if (p) hipFree(p);
+    S = nem_sim::Snap();
+  }
 }
 
-int take_snapshot(nem_sim* s) {
-  auto& S = s->snap;
+int take_snapshot(nem_sim* s, int i) {
+  auto& S = s->snap[i];
   const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
   if (!S.alloc) {
     HIPCHK(hipMalloc((void**)&S.off, sizeof(float2) * N));
@@ -279,8 +284,8 @@ int take_snapshot(nem_sim* s) {
   return NEM_OK;
 }
 
-int restore_snapshot(nem_sim* s) {
-  auto& S = s->snap;
+int restore_snapshot(nem_sim* s, int i) {
+  auto& S = s->snap[i];
   if (!S.valid) return NEM_E_STATE;
   const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
   const int p = S.parity;
@@ -562,47 +567,77 @@ int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, doub
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) return NEM_E_STATE;
   const size_t N = (size_t)s->ntot;
+  const float tauf = (float)tau;
+  unsigned tau_bits;
+  std::memcpy(&tau_bits, &tauf, sizeof(tau_bits));
   float *X = nullptr, *Y = nullptr;
-  unsigned* mx = nullptr;
-  HIPCHK(hipMalloc((void**)&X, sizeof(float) * 12 * N));
-  HIPCHK(hipMalloc((void**)&Y, sizeof(float) * 5 * N));
-  HIPCHK(hipMalloc((void**)&mx, sizeof(unsigned)));
+  unsigned *mx = nullptr, *hmx = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rc = NEM_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == NEM_OK) rc = hip_fail(s, e, what);
+    return e == hipSuccess;
+  };
+  chk(hipMalloc((void**)&X, sizeof(float) * 12 * N), "hipMalloc (inputs)");
+  chk(hipMalloc((void**)&Y, sizeof(float) * 5 * N), "hipMalloc (corrections)");
+  chk(hipMalloc((void**)&mx, sizeof(unsigned) * 2), "hipMalloc (max norm)");
+  chk(hipHostMalloc((void**)&hmx, sizeof(unsigned) * 2, hipHostMallocDefault), "hipHostMalloc (max norm)");
+  for (auto& e : ev) chk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  // One macro step, enqueued without waiting: snapshot, a step of mult*dt with
+  // the inputs captured, inference, the largest correction norm copied to the
+  // host, and the correction (skipped on the device when that norm exceeds tau).
+  auto enqueue = [&](int64_t k) -> int {
+    const int b = (int)(k & 1);
+    int e = take_snapshot(s, b);
+    if (e) return e;
+    s->feat = X;
+    e = run_steps(s, 1);
+    s->feat = nullptr;
+    if (e) return e;
+    if (!chk(hipMemsetAsync(mx + b, 0, sizeof(unsigned), s->stream), "hipMemsetAsync")) return rc;
+    launch_mlp_forward(m->P, m->hnorm, X, (int64_t)N, Y, mx + b, s->stream);
+    if (!chk(hipMemcpyAsync(hmx + b, mx + b, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync"))
+      return rc;
+    if (!chk(hipEventRecord(ev[b], s->stream), "hipEventRecord")) return rc;
+    unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
+    if (!chk(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream), "hipMemsetAsync")) return rc;
+    SortArgs a = sort_args(s, nullptr);
+    hipLaunchKernelGGL(k_correct, rep_grid(s), dim3(256), 0, s->stream, a, (const float*)Y, um,
+                       (const unsigned*)(mx + b), tau_bits);
+    chk(hipGetLastError(), "k_correct");
+    return rc;
+  };
   int64_t nfb = 0;
   float worst = 0.0f;
-  int rc = scale_dt(s, (float)mult);
-  for (int64_t it = 0; it < n_macro && !rc; ++it) {
-    rc = take_snapshot(s);
+  if (!rc) rc = scale_dt(s, (float)mult);
+  // Macro step k+1 is enqueued before the host looks at step k's norm, so the
+  // device never waits for the host. If step k needs the fallback, step k+1
+  // (speculative) is discarded with it: restore the state before step k,
+  // replay it as mult steps of dt, and enqueue step k+1 again.
+  if (!rc && n_macro > 0) rc = enqueue(0);
+  for (int64_t k = 0; k < n_macro && !rc; ++k) {
+    if (k + 1 < n_macro) rc = enqueue(k + 1);
     if (rc) break;
-    s->feat = X;
-    rc = run_steps(s, 1);
-    s->feat = nullptr;
-    if (rc) break;
-    HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), s->stream));
-    launch_mlp_forward(m->P, m->hnorm, X, (int64_t)N, Y, mx, s->stream);
-    unsigned hm = 0;
-    HIPCHK(hipMemcpyAsync(&hm, mx, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    if (!chk(hipEventSynchronize(ev[k & 1]), "hipEventSynchronize")) break;
     float fm;
-    std::memcpy(&fm, &hm, sizeof(fm));
+    std::memcpy(&fm, &hmx[k & 1], sizeof(fm));
     worst = std::max(worst, fm);
-    if (!(fm <= (float)tau)) {
-      // discard: replay the macro step as mult steps of dt
+    if (!(fm <= tauf)) {
       ++nfb;
-      rc = restore_snapshot(s);
+      if (!chk(hipStreamSynchronize(s->stream), "hipStreamSynchronize")) break;
+      rc = restore_snapshot(s, (int)(k & 1));
       if (!rc) rc = scale_dt(s, 1.0f / (float)mult);
       if (!rc) rc = run_steps(s, mult);
       if (!rc) rc = scale_dt(s, (float)mult);
-      continue;
+      if (!rc && k + 1 < n_macro) rc = enqueue(k + 1);
     }
-    unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
-    HIPCHK(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream));
-    SortArgs a = sort_args(s, nullptr);
-    hipLaunchKernelGGL(k_correct, rep_grid(s), dim3(256), 0, s->stream, a, Y, um);
-    HIPCHK(hipGetLastError());
   }
   if (!rc) rc = scale_dt(s, 1.0f / (float)mult);
   hipStreamSynchronize(s->stream);
+  for (auto& e : ev)
+    if (e) hipEventDestroy(e);
   hipFree(X); hipFree(Y); hipFree(mx);
+  if (hmx) hipHostFree(hmx);
   if (n_fallback) *n_fallback = nfb;
   if (max_norm) *max_norm = worst;
   if (rc) return rc;

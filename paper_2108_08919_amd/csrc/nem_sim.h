@@ -64,7 +64,7 @@ struct nem_sim {
     unsigned* umax = nullptr;  // R * UMAX_SLOTS max-speed slots, then the rebin request
     int parity = 0;
     std::vector<float> dt;
-  } snap;
+  } snap[2];  // two, so that a learned macro step can run while the previous one is checked
   std::string err;
 };
 
@@ -88,8 +88,8 @@ int status_from_flags(nem_sim* s, unsigned f);
 int run_steps(nem_sim* s, int64_t nsteps);
 int upload_reps(nem_sim* s);
 void free_snapshot(nem_sim* s);
-int take_snapshot(nem_sim* s);
-int restore_snapshot(nem_sim* s);
+int take_snapshot(nem_sim* s, int i = 0);
+int restore_snapshot(nem_sim* s, int i = 0);
 int build_work(nem_sim* s);
 void drop_graphs(nem_sim* s);
 
