@@ -151,11 +151,22 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out);
  *   slope of ln E on ln n over k_lo..k_hi (<= 0 selects 4 and M/8).
  * nem_defects: counts of +1/2 and -1/2 defects: director angle atan2(Qxy,Qxx)/2
  *   per node, winding around each unit plaquette with edge differences wrapped
- *   into (-pi/2, pi/2]; a total of +pi (-pi) is a +1/2 (-1/2) defect. */
+ *   into (-pi/2, pi/2]; a total of +pi (-pi) is a +1/2 (-1/2) defect.
+ * nem_vorticity_correlation: normalised vorticity-vorticity correlation
+ *   (paper Sec. 5, Eq. corr) of the grid field omega = d uy/dx - d ux/dy, taken
+ *   spectrally (omega^ = i (kx u^y - ky u^x), the Nyquist wavenumber set to
+ *   zero), averaged over all points of the periodic grid:
+ *   C(r) = <omega(x + r) omega(x)> / <omega^2>, from a second FFT of |omega^|^2.
+ *   c_x[n] and c_y[n] (caller arrays of M/2 + 1 doubles) hold C at separations
+ *   n L/M along x and along y; *l_x, *l_y (may be NULL) the first zero crossing
+ *   of each, linearly interpolated, in length units (-1 if C stays positive up
+ *   to L/2). A field with omega = 0 gives NaN. */
 int nem_deposit(nem_sim* s, int32_t r, int32_t M, double* out);
 int nem_spectrum(nem_sim* s, int32_t r, int32_t M, double* E, int32_t nbins, int32_t k_lo, int32_t k_hi,
                  double* slope);
 int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus);
+int nem_vorticity_correlation(nem_sim* s, int32_t r, int32_t M, double* c_x, double* c_y, double* l_x,
+                              double* l_y);
 
 /* Tuning and instrumentation options (key, value):
  *   NEM_OPT_TILE       cells per tile side (4 or 8)

@@ -10,6 +10,14 @@ Readings (the paper gives no formulas for either):
 * defects: director angle theta = atan2(Qxy, Qxx)/2 on the grid; around each
   unit plaquette add the four edge differences of theta, each wrapped into
   (-pi/2, pi/2]; a total of +pi is a +1/2 defect, -pi a -1/2 defect.
+* vorticity correlation (Eq. corr): the paper fixes C(r) = <f(r) f(0)> / f(0)^2
+  with f the vorticity and r along the horizontal centre line; in a periodic
+  box every point can serve as the origin, so the average runs over all grid
+  points: C(r) = <omega(x + r) omega(x)>_x / <omega^2>_x, reported along x (the
+  paper's direction) and along y. omega = d uy/dx - d ux/dy on the grid is taken
+  spectrally, omega_hat = i (kx uy_hat - ky ux_hat) with k = 2 pi n / L, the
+  Nyquist wavenumber n = -M/2 set to zero. The length scale is the first zero
+  crossing of C, linearly interpolated between grid separations.
 The FFT is numpy's (a library primitive); everything else is written out.
 """
 from __future__ import annotations
@@ -76,3 +84,46 @@ def defects(params, x, y, qxx, qxy, M: int):
     g = deposit(params, x, y, [qxx, qxy], M)
     p, m, _ = defects_from_grid(g[0], g[1])
     return p, m
+
+
+def vorticity_from_grid(ux: np.ndarray, uy: np.ndarray, L: float) -> np.ndarray:
+    """omega = d uy/dx - d ux/dy of grid fields (rows = y, columns = x)."""
+    M = ux.shape[0]
+    n = np.fft.fftfreq(M) * M
+    n[M // 2] = 0.0                             # the Nyquist wavenumber has no derivative
+    k = 2.0 * math.pi * n / L
+    KX, KY = np.meshgrid(k, k, indexing="xy")   # KX varies along columns (x)
+    w_hat = 1j * (KX * np.fft.fft2(uy) - KY * np.fft.fft2(ux))
+    return np.real(np.fft.ifft2(w_hat))
+
+
+def autocorrelation(f: np.ndarray) -> np.ndarray:
+    """A[ry, rx] = mean over grid points x of f(x + r) f(x) (periodic), from the
+    power spectrum (Wiener-Khinchin)."""
+    M = f.shape[0]
+    F = np.fft.fft2(f)
+    return np.real(np.fft.ifft2(np.abs(F) ** 2)) / float(M * M)
+
+
+def first_zero(c: np.ndarray, dl: float) -> float:
+    for n in range(1, c.size):
+        if c[n] <= 0.0:
+            return (n - 1 + c[n - 1] / (c[n - 1] - c[n])) * dl
+    return -1.0
+
+
+def vorticity_correlation_from_grid(ux: np.ndarray, uy: np.ndarray, L: float):
+    """(C_x, C_y, l_x, l_y) for separations n L/M, n = 0..M/2."""
+    M = ux.shape[0]
+    A = autocorrelation(vorticity_from_grid(ux, uy, L))
+    H = M // 2
+    cx = A[0, :H + 1] / A[0, 0]
+    cy = A[:H + 1, 0] / A[0, 0]
+    dl = L / M
+    return cx, cy, first_zero(cx, dl), first_zero(cy, dl)
+
+
+def vorticity_correlation(params, x, y, ux, uy, M: int):
+    from . import deposit
+    g = deposit(params, x, y, [ux, uy], M)
+    return vorticity_correlation_from_grid(g[0], g[1], params.L)

@@ -43,7 +43,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_set_option", "nem_pass_times", "nem_strerror", "nem_last_error", "nem_destroy",
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
-            "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune")
+            "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation")
 
 
 class NemParams(C.Structure):
@@ -105,6 +105,8 @@ def lib(path: Optional[str] = None):
     L.nem_spectrum.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, C.c_int32, dp]
     L.nem_defects.restype = C.c_int
     L.nem_defects.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.nem_vorticity_correlation.restype = C.c_int
+    L.nem_vorticity_correlation.argtypes = [vp, C.c_int32, C.c_int32, dp, dp, dp, dp]
     L.nem_set_option.restype = C.c_int
     L.nem_set_option.argtypes = [vp, C.c_int32, C.c_int64]
     L.nem_pass_times.restype = C.c_int
@@ -260,6 +262,15 @@ def nem_defects(h, r, M):
     return a.value, b.value
 
 
+def nem_vorticity_correlation(h, r, M):
+    cx = np.zeros(M // 2 + 1)
+    cy = np.zeros(M // 2 + 1)
+    lx, ly = C.c_double(0), C.c_double(0)
+    _check(h, lib().nem_vorticity_correlation(C.c_void_p(h), r, M, _dp(cx), _dp(cy), C.byref(lx), C.byref(ly)),
+           "nem_vorticity_correlation")
+    return cx, cy, lx.value, ly.value
+
+
 def nem_set_option(h, key: int, value: int):
     _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
 
@@ -409,6 +420,16 @@ class Sim:
 
     def defects(self, r: int = 0, M: int = 0):
         return nem_defects(self.h, r, M or int(self.params[r].L))
+
+    def vorticity_correlation(self, r: int = 0, M: int = 0):
+        """(C_x, C_y, l_x, l_y): vorticity autocorrelation along x and y on the
+        M x M deposit grid and their first zero crossings (length units)."""
+        return nem_vorticity_correlation(self.h, r, M or int(self.params[r].L))
+
+    def vrms(self, r: int = 0):
+        """Root mean square speed over the particles, sqrt(2 KE) with
+        KE = sum |u|^2 / (2N) at the integer time level."""
+        return float(np.sqrt(2.0 * nem_diagnostics(self.h, r)["ke"]))
 
     def samples(self, mult: int = 4):
         """Training inputs X (ntot x 12) and targets T (ntot x 5) at the current state."""

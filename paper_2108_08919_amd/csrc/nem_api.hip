@@ -674,6 +674,40 @@ int nem_spectrum(nem_sim* s, int32_t r, int32_t M, double* E, int32_t nbins, int
   return status_from_flags(s, f[0]);
 }
 
+int nem_vorticity_correlation(nem_sim* s, int32_t r, int32_t M, double* c_x, double* c_y, double* l_x,
+                              double* l_y) {
+  if (!s || !c_x || !c_y) return NEM_E_INVAL;
+  int rc = deposit_grid(s, r, M);
+  if (rc) return rc;
+  int logM = 0;
+  while ((1 << logM) < M) ++logM;
+  launch_fft2(s->g_grid, s->g_z, s->g_w, M, logM, s->stream);
+  launch_vort_correlation(s->g_w, M, logM, s->hp[r].L, s->g_z, s->g_w, s->g_part, s->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(M + 2);
+  HIPCHK(hipMemcpyAsync(h.data(), s->g_part, sizeof(double) * (M + 2), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const int H = M / 2;
+  const double a0 = h[0];
+  const double dl = s->hp[r].L / M;
+  // first zero crossing, linearly interpolated; -1 when the curve stays positive
+  auto crossing = [&](const double* c) {
+    for (int n = 1; n <= H; ++n)
+      if (c[n] <= 0.0) return (n - 1 + c[n - 1] / (c[n - 1] - c[n])) * dl;
+    return -1.0;
+  };
+  for (int n = 0; n <= H; ++n) {
+    c_x[n] = a0 > 0.0 ? h[n] / a0 : NAN;
+    c_y[n] = a0 > 0.0 ? h[H + 1 + n] / a0 : NAN;
+  }
+  if (l_x) *l_x = a0 > 0.0 ? crossing(c_x) : NAN;
+  if (l_y) *l_y = a0 > 0.0 ? crossing(c_y) : NAN;
+  unsigned f[2];
+  rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
 int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus) {
   if (!s || !n_plus || !n_minus) return NEM_E_INVAL;
   int rc = deposit_grid(s, r, M);

@@ -122,6 +122,8 @@ void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st);
 void launch_deposit(int T, const StepArgs& a, int rep, int M, double* grid, hipStream_t s);
 void launch_fft2(const double* grid, double2* z, double2* w, int M, int logM, hipStream_t s);
 void launch_shells(const double2* Z, int M, int nbins, double* part, double* E, hipStream_t s);
+void launch_vort_correlation(const double2* W, int M, int logM, double L, double2* z, double2* w, double* axes,
+                             hipStream_t s);
 void launch_winding(const double* grid, int M, unsigned long long* counts, hipStream_t s);
 
 }  // namespace nem

@@ -198,6 +198,52 @@ void launch_deposit(int T, const StepArgs& a, int rep, int M, double* grid, hipS
   else hipLaunchKernelGGL((k_deposit<4>), grid_, block, 0, s, a, rep, M, grid);
 }
 
+// |omega^(k)|^2 of the vorticity omega = d uy/dx - d ux/dy from the 2D FFT
+// W of z = ux + i uy (W[a*M + b] = Z(kx index a, ky index b), as launch_fft2
+// leaves it): u^x(k) = (Z(k) + conj Z(-k))/2, u^y(k) = (Z(k) - conj Z(-k))/(2i),
+// omega^ = i (kx u^y - ky u^x) with k = 2 pi n / L; the Nyquist wavenumber
+// (n = -M/2) has no derivative on the grid and is set to zero. P keeps the
+// (kx, ky) layout, as a complex array with zero imaginary part.
+__global__ void k_vort_power(const double2* W, int M, double L, double2* P) {
+  const size_t MM = (size_t)M * M;
+  const double tpl = 2.0 * M_PI / L;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < MM; k += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(k / M), b = (int)(k % M);
+    const int na = (a < M / 2) ? a : a - M, nb = (b < M / 2) ? b : b - M;
+    const double kx = (na == -M / 2) ? 0.0 : tpl * na, ky = (nb == -M / 2) ? 0.0 : tpl * nb;
+    const double2 z = W[k], zm = W[(size_t)((M - a) % M) * M + (M - b) % M];
+    const double uxr = 0.5 * (z.x + zm.x), uxi = 0.5 * (z.y - zm.y);  // (Z + conj Zm) / 2
+    const double uyr = 0.5 * (z.y + zm.y), uyi = -0.5 * (z.x - zm.x);  // (Z - conj Zm) / (2i)
+    // omega^ = i (kx u^y - ky u^x): |omega^|^2 = |kx u^y - ky u^x|^2
+    const double wr = kx * uyr - ky * uxr, wi = kx * uyi - ky * uxi;
+    P[k] = make_double2(wr * wr + wi * wi, 0.0);
+  }
+}
+
+// Row 0 and column 0 of the M x M grid V (real parts): out[0..M/2] = V[0][n],
+// out[M/2+1..M+1] = V[n][0].
+__global__ void k_grid_axes(const double2* V, int M, double* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > M / 2) return;
+  out[n] = V[n].x;
+  out[M / 2 + 1 + n] = V[(size_t)n * M].x;
+}
+
+void launch_vort_correlation(const double2* W, int M, int logM, double L, double2* z, double2* w, double* axes,
+                             hipStream_t s) {
+  const size_t MM = (size_t)M * M;
+  const int nb = (int)std::min<size_t>((MM + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_vort_power, dim3(nb), dim3(256), 0, s, W, M, L, z);
+  // second 2D FFT: rows of P (along ky), transpose, rows (along kx); the result
+  // V[ry*M + rx] = sum_k P(k) e^{-i k.r} is M^4 times the periodic autocorrelation
+  const size_t lds = sizeof(double2) * M;
+  hipLaunchKernelGGL(k_fft_rows, dim3(M), dim3(256), lds, s, z, M, logM);
+  const dim3 tg((M + 31) / 32, (M + 31) / 32), tb(32, 8);
+  hipLaunchKernelGGL(k_transpose, tg, tb, 0, s, (const double2*)z, w, M);
+  hipLaunchKernelGGL(k_fft_rows, dim3(M), dim3(256), lds, s, w, M, logM);
+  hipLaunchKernelGGL(k_grid_axes, dim3((M / 2 + 1 + 255) / 256), dim3(256), 0, s, (const double2*)w, M, axes);
+}
+
 void launch_fft2(const double* grid, double2* z, double2* w, int M, int logM, hipStream_t s) {
   const size_t MM = (size_t)M * M;
   const int nb = (int)std::min<size_t>((MM + 255) / 256, 4096);

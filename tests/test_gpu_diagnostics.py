@@ -140,3 +140,82 @@ def test_defects_analytic_pair():
     sim.set_state(0, st)
     assert sim.defects(0, 64) == (1, 1)
     sim.close()
+
+
+def _smooth_velocity(L, x, y, seed, nmax=4, amp=1e-3):
+    """Sum of random Fourier modes with |n| <= nmax: a field with a finite
+    vorticity correlation length."""
+    rng = np.random.default_rng(seed)
+    ux = np.zeros_like(x)
+    uy = np.zeros_like(x)
+    for nx in range(-nmax, nmax + 1):
+        for ny in range(0, nmax + 1):
+            if (nx, ny) == (0, 0):
+                continue
+            ph = 2 * math.pi * (nx * x + ny * y) / L
+            a, b, c, d = rng.normal(size=4)
+            ux += a * np.cos(ph) + b * np.sin(ph)
+            uy += c * np.cos(ph) + d * np.sin(ph)
+    s = amp / np.sqrt(np.mean(ux ** 2 + uy ** 2))
+    return ux * s, uy * s
+
+
+def test_vorticity_correlation_matches_oracle():
+    L = 64
+    p = wl.Params(L=float(L), zeta=0.03)
+    x, y = wl.lattice(L)
+    n = x.size
+    rng = np.random.default_rng(14)
+    x = (x + 0.05 * rng.uniform(-1, 1, n)) % L
+    y = (y + 0.05 * rng.uniform(-1, 1, n)) % L
+    ux, uy = _smooth_velocity(L, x, y, 15)
+    th = rng.uniform(0, math.pi, n)
+    z = np.zeros(n)
+    st = dict(x=x, y=y, ux=ux, uy=uy, qxx=np.cos(2 * th), qxy=np.sin(2 * th), rho=np.ones(n), ax=z, ay=z)
+    import paper_2108_08919_amd as P
+    sim = P.Sim([p], [n])
+    sim.set_state(0, st)
+    sim.step(2)
+    g = sim.get_state(0)
+    for M in (32, 64):
+        cx, cy, lx, ly = sim.vorticity_correlation(0, M)
+        assert cx.size == M // 2 + 1 and cx[0] == 1.0 and cy[0] == 1.0
+        # FFTs and axes: GPU against numpy on the GPU's own deposit grid
+        G = sim.deposit(0, M)
+        ex, ey, mx, my = diag.vorticity_correlation_from_grid(G[0], G[1], float(L))
+        assert np.abs(cx - ex).max() < 1e-9 and np.abs(cy - ey).max() < 1e-9
+        assert (lx, ly) == pytest.approx((mx, my), abs=1e-7)
+        # whole pipeline against the FP64 oracle deposit of the same particles
+        ox, oy, olx, oly = diag.vorticity_correlation(p, g["x"], g["y"], g["ux"], g["uy"], M)
+        print(M, lx, olx, ly, oly, np.abs(cx - ox).max(), np.abs(cy - oy).max(), flush=True)
+        assert np.abs(cx - ox).max() < 1e-5 and np.abs(cy - oy).max() < 1e-5
+        assert lx > 0 and ly > 0
+        assert (lx, ly) == pytest.approx((olx, oly), rel=1e-4)
+    sim.close()
+
+
+def test_vorticity_correlation_single_mode():
+    L = 64
+    p = wl.Params(L=float(L), zeta=0.0, K=0.0, eta=0.0, apd=0)
+    x, y = wl.lattice(L)
+    n = x.size
+    z = np.zeros(n)
+    m = 2
+    uy = 1e-3 * np.sin(2 * math.pi * m * x / L)
+    st = dict(x=x, y=y, ux=z, uy=uy, qxx=np.ones(n), qxy=z, rho=np.ones(n), ax=z, ay=z)
+    import paper_2108_08919_amd as P
+    sim = P.Sim([p], [n])
+    sim.set_state(0, st)
+    cx, cy, lx, ly = sim.vorticity_correlation(0, 64)
+    k = np.arange(33)
+    assert np.abs(cx - np.cos(2 * math.pi * m * k / 64)).max() < 1e-6
+    assert np.abs(cy - 1.0).max() < 1e-6
+    assert lx == pytest.approx(L / (4 * m), rel=1e-6)
+    assert ly == -1.0
+    # a field with no vorticity has no normalised correlation
+    st["uy"] = z
+    sim.set_state(0, st)
+    cx, cy, lx, ly = sim.vorticity_correlation(0, 64)
+    assert np.isnan(cx).all() and np.isnan(lx)
+    assert sim.vrms(0) == 0.0
+    sim.close()

@@ -85,3 +85,69 @@ def test_deposit_reproduces_constant_and_linear():
     x, y = wl.jittered_lattice(L, 1.0, 0.3, 3)
     g = oracle.deposit(p, x, y, [np.full(x.size, 2.5)], 32)
     assert np.abs(g - 2.5).max() < 1e-14
+
+
+def _grid(M, L):
+    j, i = np.meshgrid(np.arange(M), np.arange(M), indexing="ij")
+    return (i + 0.5) * (L / M), (j + 0.5) * (L / M)   # x varies along columns, y along rows
+
+
+@pytest.mark.parametrize("m", [1, 2, 5])
+def test_vorticity_correlation_single_mode(m):
+    """uy = U sin(k x): omega = U k cos(k x), whose normalised autocorrelation is
+    cos(k r) along x (zero at L/4m) and 1 along y."""
+    M, L, U = 64, 64.0, 0.3
+    x, y = _grid(M, L)
+    k = 2 * math.pi * m / L
+    ux, uy = np.zeros((M, M)), U * np.sin(k * x)
+    w = diag.vorticity_from_grid(ux, uy, L)
+    assert np.abs(w - U * k * np.cos(k * x)).max() < 1e-12 * U * k
+    cx, cy, lx, ly = diag.vorticity_correlation_from_grid(ux, uy, L)
+    n = np.arange(M // 2 + 1)
+    assert np.abs(cx - np.cos(2 * math.pi * m * n / M)).max() < 1e-12
+    assert np.abs(cy - 1.0).max() < 1e-12
+    # zero of cos between grid shifts n0 and n0+1, linearly interpolated
+    c = np.cos(2 * math.pi * m * n / M)
+    n0 = int(np.argmax(c <= 0)) - 1
+    lx_lin = (n0 + c[n0] / (c[n0] - c[n0 + 1])) * (L / M)
+    assert lx == pytest.approx(lx_lin, rel=1e-9)
+    if (M % (4 * m)) == 0:
+        assert lx == pytest.approx(L / (4 * m), rel=1e-9)
+    assert ly == -1.0
+    A = diag.autocorrelation(w)
+    assert A[0, 0] == pytest.approx(0.5 * (U * k) ** 2, rel=1e-12)
+
+
+def test_vorticity_of_two_dimensional_field():
+    """A field varying in both directions against its analytic curl."""
+    M, L = 32, 32.0
+    x, y = _grid(M, L)
+    a, b = 2 * math.pi / L, 2 * math.pi * 3 / L
+    ux = np.sin(b * y) * np.cos(a * x)
+    uy = 0.5 * np.cos(2 * a * x) * np.sin(a * y)
+    w_exact = -a * np.sin(2 * a * x) * np.sin(a * y) * 1.0 - b * np.cos(b * y) * np.cos(a * x)
+    assert np.abs(diag.vorticity_from_grid(ux, uy, L) - w_exact).max() < 1e-12
+
+
+def test_autocorrelation_equals_direct_sum():
+    """Wiener-Khinchin route against the direct periodic sum over all shifts."""
+    rng = np.random.default_rng(5)
+    M = 12
+    f = rng.normal(size=(M, M))
+    A = diag.autocorrelation(f)
+    D = np.zeros((M, M))
+    for ry in range(M):
+        for rx in range(M):
+            D[ry, rx] = np.mean(np.roll(np.roll(f, -ry, axis=0), -rx, axis=1) * f)
+    assert np.abs(A - D).max() < 1e-12
+
+
+def test_vorticity_correlation_axes_swap_under_transposition():
+    """Reflecting the field across the diagonal (x <-> y) swaps C_x and C_y."""
+    rng = np.random.default_rng(6)
+    M, L = 32, 32.0
+    ux, uy = rng.normal(size=(M, M)), rng.normal(size=(M, M))
+    cx, cy, lx, ly = diag.vorticity_correlation_from_grid(ux, uy, L)
+    tx, ty, mx, my = diag.vorticity_correlation_from_grid(uy.T.copy(), ux.T.copy(), L)
+    assert np.abs(tx - cy).max() < 1e-12 and np.abs(ty - cx).max() < 1e-12
+    assert (mx, my) == pytest.approx((ly, lx), abs=1e-12)
