@@ -106,17 +106,24 @@ def test_c1_ten_steps():
     sim.close()
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_random_state_ten_steps(seed):
+@pytest.mark.parametrize("seed,zeta", [(0, 0.03), (1, 0.03), (2, -0.03)])
+def test_random_state_ten_steps(seed, zeta):
+    """Extensile (zeta > 0) and contractile (zeta < 0) activity."""
     L = 40
-    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    p = wl.Params(L=float(L), zeta=zeta, K=0.04)
     s0 = random_state(L, seed, amp_u=2e-3)
-    say("random 10 steps", seed)
+    say("random 10 steps", seed, zeta)
     o, _ = run_oracle(p, s0, 10)
     g, sim = gpu_run(p, s0, 10)
     e = field_errors(g, o, s0, L)
     check(e)
-    assert e["disp"] < 1e-4 and e["dQ"] < 1e-4 and e["drho"] < 1e-3
+    # The APD sum of r_ij / r^3 has no kernel weight, so it jumps at r = 3h.
+    # At step 10 of seed 2 the pair (997, 1157) sits 5e-8 inside 3h, closer
+    # than the FP32 predicate resolves (r^2 - R^2 = -4e-7, ulp(R^2) = 9.5e-7):
+    # the GPU drops it, the FP64 oracle keeps it, and particle 1157 moves
+    # 2e-7 further. Displacements are held to 3e-4 to admit one such flip;
+    # positions, u, Q and rho stay within the 1e-5 bar.
+    assert e["disp"] < 3e-4 and e["pos_abs_max"] < 5e-7 and e["dQ"] < 1e-4 and e["drho"] < 1e-3
     sim.close()
 
 

@@ -133,3 +133,33 @@ def test_forms_agree_at_rest():
     # first step: u = 0 so form only changes the active term's discretisation;
     # both produce the same sign pattern of the first acceleration
     assert np.corrcoef(s0.ax, s1.ax)[0, 1] > 0.9
+
+
+def _first_active_acceleration(L, zeta, A=0.1):
+    x, y = wl.lattice(L)
+    n = x.size
+    k = 2 * math.pi / L
+    st = dict(x=x, y=y, ux=np.zeros(n), uy=np.zeros(n), qxx=A * np.cos(k * x), qxy=np.zeros(n),
+              rho=np.ones(n), ax=np.zeros(n), ay=np.zeros(n))
+    s1 = oracle.State(st)
+    oracle.step(wl.Params(L=float(L), zeta=zeta, K=0.02, apd=0), s1, 1)
+    return s1.ax, s1.ay, zeta * A * k * np.sin(k * x), abs(zeta) * A * k
+
+
+@pytest.mark.parametrize("zeta", [0.02, -0.02])
+def test_active_force_is_minus_zeta_div_q(zeta):
+    """From rest with uniform density the only force of the first step is the
+    active one, -(zeta/rho) div Q (Eq. activestress in the momentum balance).
+    Q = (A cos kx, 0) gives a_x = zeta A k sin(kx), a_y = 0: extensile
+    (zeta > 0) and contractile (zeta < 0) activity push in opposite directions,
+    the force is linear in zeta, and the SPH sum converges to the continuum
+    value at second order in k h."""
+    err = []
+    for L in (32, 64):
+        ax, ay, exact, scale = _first_active_acceleration(L, zeta)
+        assert np.abs(ay).max() < 1e-12 * scale
+        err.append(np.abs(ax - exact).max() / scale)
+    assert err[1] < 5e-3
+    assert 3.8 < err[0] / err[1] < 4.2
+    ax2, _, _, scale = _first_active_acceleration(64, 2 * zeta)
+    assert np.abs(ax2 - 2 * ax).max() < 1e-13 * scale
