@@ -168,6 +168,32 @@ int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_mi
 int nem_vorticity_correlation(nem_sim* s, int32_t r, int32_t M, double* c_x, double* c_y, double* l_x,
                               double* l_y);
 
+/* Lagrangian diagnostics (paper Sec. 5: pathlines of tagged particles, mixing
+ * of colour-marked regions).
+ *
+ * nem_track: unwrapped positions at the integer time level of the particles
+ *   ids[0..n_ids) of replica r (ids are the indices of nem_set_state), written
+ *   to the caller's x[n_ids], y[n_ids]. Each particle carries a periodic image
+ *   counter: it is set by nem_set_state from the coordinates given (positions
+ *   outside [0, L) count as images, so a state set from unwrapped coordinates
+ *   reads back unwrapped) and changes by one each time the particle crosses the
+ *   periodic boundary, so x + L img_x follows the particle through any number
+ *   of crossings. NEM_E_INVAL for ids out of [0, n) or n_ids > n.
+ * nem_mixing: colour histogram and mixing index of replica r. colour[id]
+ *   (caller array of n bytes, values < ncol <= 255) marks each particle, for
+ *   instance by the quadrant of its initial position. The box is cut into
+ *   B x B equal bins (B <= 1024) and counts[(by B + bx) ncol + c] (caller array
+ *   of B*B*ncol, may be NULL) receives the number of particles of colour c in
+ *   bin (bx, by), bx = floor(x B / L) of the wrapped position. *index (may be
+ *   NULL) = 1 - I with I Danckwerts' intensity of segregation,
+ *   I = sum_b sum_c N_b (phi_cb - phi_c)^2 / sum_c N phi_c (1 - phi_c),
+ *   phi_cb = N_cb / N_b the colour fractions of bin b and phi_c = N_c / N the
+ *   box fractions: 0 while every bin holds one colour, 1 when every bin holds
+ *   the box's mixture; NaN with a single colour. */
+int nem_track(nem_sim* s, int32_t r, const int32_t* ids, int32_t n_ids, double* x, double* y);
+int nem_mixing(nem_sim* s, int32_t r, const uint8_t* colour, int32_t ncol, int32_t B, int64_t* counts,
+               double* index);
+
 /* Tuning and instrumentation options (key, value):
  *   NEM_OPT_TILE       cells per tile side (4 or 8)
  *   NEM_OPT_LPP        lanes per particle in the pair loops (1, 2 or 4)

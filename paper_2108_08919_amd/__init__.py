@@ -43,7 +43,8 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_set_option", "nem_pass_times", "nem_strerror", "nem_last_error", "nem_destroy",
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
-            "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation")
+            "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
+            "nem_track", "nem_mixing")
 
 
 class NemParams(C.Structure):
@@ -107,6 +108,10 @@ def lib(path: Optional[str] = None):
     L.nem_defects.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.nem_vorticity_correlation.restype = C.c_int
     L.nem_vorticity_correlation.argtypes = [vp, C.c_int32, C.c_int32, dp, dp, dp, dp]
+    L.nem_track.restype = C.c_int
+    L.nem_track.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32, dp, dp]
+    L.nem_mixing.restype = C.c_int
+    L.nem_mixing.argtypes = [vp, C.c_int32, C.POINTER(C.c_uint8), C.c_int32, C.c_int32, C.POINTER(C.c_int64), dp]
     L.nem_set_option.restype = C.c_int
     L.nem_set_option.argtypes = [vp, C.c_int32, C.c_int64]
     L.nem_pass_times.restype = C.c_int
@@ -271,6 +276,24 @@ def nem_vorticity_correlation(h, r, M):
     return cx, cy, lx.value, ly.value
 
 
+def nem_track(h, r, ids):
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    x = np.zeros(ids.size)
+    y = np.zeros(ids.size)
+    _check(h, lib().nem_track(C.c_void_p(h), r, ids.ctypes.data_as(C.POINTER(C.c_int32)), ids.size, _dp(x), _dp(y)),
+           "nem_track")
+    return x, y
+
+
+def nem_mixing(h, r, colour, ncol, B):
+    colour = np.ascontiguousarray(colour, dtype=np.uint8)
+    counts = np.zeros(B * B * ncol, dtype=np.int64)
+    idx = C.c_double(0)
+    _check(h, lib().nem_mixing(C.c_void_p(h), r, colour.ctypes.data_as(C.POINTER(C.c_uint8)), ncol, B,
+                               counts.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(idx)), "nem_mixing")
+    return idx.value, counts.reshape(B, B, ncol)
+
+
 def nem_set_option(h, key: int, value: int):
     _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
 
@@ -425,6 +448,16 @@ class Sim:
         """(C_x, C_y, l_x, l_y): vorticity autocorrelation along x and y on the
         M x M deposit grid and their first zero crossings (length units)."""
         return nem_vorticity_correlation(self.h, r, M or int(self.params[r].L))
+
+    def track(self, ids, r: int = 0):
+        """Unwrapped positions (x, y) of the particles `ids` at the integer time level."""
+        return nem_track(self.h, r, ids)
+
+    def mixing(self, colour, ncol: int, B: int, r: int = 0):
+        """(mixing index, counts[by, bx, colour]) of the colouring `colour` (by id) on B x B bins."""
+        if len(colour) != self.n[r]:
+            raise ValueError("one colour per particle")
+        return nem_mixing(self.h, r, colour, ncol, B)
 
     def vrms(self, r: int = 0):
         """Root mean square speed over the particles, sqrt(2 KE) with

@@ -82,8 +82,8 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
 // Offsets of every buffer for given sizes (shared by nem_arena_bytes and carve()).
 struct Offs {
   size_t reps, work, cell_start, count, cursor, perm;
-  size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id;
-  size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell;
+  size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id, t_img;
+  size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell, img;
   size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe, vl, vcnt, off_build;
   size_t total;
 };
@@ -106,6 +106,7 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.t_drho = L.put(sizeof(float) * N);
   o.t_acc = L.put(sizeof(float2) * N);
   o.t_id = L.put(sizeof(int) * N);
+  o.t_img = L.put(sizeof(int2) * N);
   o.off0 = L.put(sizeof(float2) * N);
   o.off1 = L.put(sizeof(float2) * N);
   o.offlo = L.put(sizeof(float2) * N);
@@ -116,6 +117,7 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.acc = L.put(sizeof(float2) * N);
   o.id = L.put(sizeof(int) * N);
   o.cell = L.put(sizeof(int) * N);
+  o.img = L.put(sizeof(int2) * N);
   o.V = L.put(sizeof(float) * N);
   o.bk = L.put(sizeof(float4) * N);
   o.dh = L.put(sizeof(float) * N);
@@ -165,9 +167,9 @@ SortArgs sort_args(nem_sim* s, const unsigned* gate) {
   a.reps = s->d_reps; a.R = s->R; a.ncells = s->ncells; a.ntot = s->ntot;
   a.cell_start = s->cell_start; a.count = s->count; a.cursor = s->cursor; a.perm = s->perm;
   a.t_key = s->t_key; a.t_off = s->t_off; a.t_lo = s->t_lo; a.t_u = s->t_u; a.t_q = s->t_q;
-  a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id;
+  a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id; a.t_img = s->t_img;
   a.off = s->off[s->parity]; a.offlo = s->offlo; a.u = s->u; a.q = s->q[s->parity];
-  a.drho = s->drho; a.acc = s->acc; a.id = s->id; a.cell = s->cell;
+  a.drho = s->drho; a.acc = s->acc; a.id = s->id; a.cell = s->cell; a.img = s->img;
   a.flags = s->flags; a.gate = gate; a.off_build = s->off_build;
   return a;
 }
@@ -456,11 +458,11 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   s->cursor = (int*)(b + o.cursor); s->perm = (int*)(b + o.perm);
   s->t_key = (int*)(b + o.t_key); s->t_off = (float2*)(b + o.t_off); s->t_lo = (float2*)(b + o.t_lo);
   s->t_u = (float2*)(b + o.t_u); s->t_q = (float2*)(b + o.t_q); s->t_drho = (float*)(b + o.t_drho);
-  s->t_acc = (float2*)(b + o.t_acc); s->t_id = (int*)(b + o.t_id);
+  s->t_acc = (float2*)(b + o.t_acc); s->t_id = (int*)(b + o.t_id); s->t_img = (int2*)(b + o.t_img);
   s->off[0] = (float2*)(b + o.off0); s->off[1] = (float2*)(b + o.off1); s->offlo = (float2*)(b + o.offlo);
   s->u = (float2*)(b + o.u); s->q[0] = (float2*)(b + o.q0); s->q[1] = (float2*)(b + o.q1);
   s->drho = (float*)(b + o.drho); s->acc = (float2*)(b + o.acc); s->id = (int*)(b + o.id);
-  s->cell = (int*)(b + o.cell);
+  s->cell = (int*)(b + o.cell); s->img = (int2*)(b + o.img);
   s->V = (float*)(b + o.V); s->bk = (float4*)(b + o.bk); s->dh = (float*)(b + o.dh);
   s->apart = (float2*)(b + o.apart); s->uv = (float*)(b + o.uv); s->pi = (float2*)(b + o.pi);
   s->P = (float*)(b + o.P); s->drhat = (float*)(b + o.drhat);
@@ -708,6 +710,83 @@ int nem_vorticity_correlation(nem_sim* s, int32_t r, int32_t M, double* c_x, dou
   return status_from_flags(s, f[0]);
 }
 
+int nem_track(nem_sim* s, int32_t r, const int32_t* ids, int32_t n_ids, double* x, double* y) {
+  if (!s || r < 0 || r >= s->R || n_ids < 0 || (n_ids > 0 && (!ids || !x || !y))) return NEM_E_INVAL;
+  if (!s->has_state[r]) { s->err = "state of this replica was never set"; return NEM_E_STATE; }
+  const int n = (int)s->n[r];
+  if (n_ids > n) { s->err = "more ids than particles"; return NEM_E_INVAL; }
+  for (int t = 0; t < n_ids; ++t)
+    if (ids[t] < 0 || ids[t] >= n) { s->err = "particle id out of range"; return NEM_E_INVAL; }
+  if (n_ids == 0) return NEM_OK;
+  // staging (9 n doubles): inv[n] ints at 0, ids at n doubles, output at 2n doubles
+  int* inv = (int*)s->stage;
+  int* d_ids = (int*)(s->stage + n);
+  double* out = s->stage + 2 * (size_t)n;
+  HIPCHK(hipMemcpyAsync(d_ids, ids, sizeof(int32_t) * n_ids, hipMemcpyHostToDevice, s->stream));
+  SortArgs a = sort_args(s, nullptr);
+  launch_track(a, r, n, inv, d_ids, n_ids, out, s->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(x, out, sizeof(double) * n_ids, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(y, out + n_ids, sizeof(double) * n_ids, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_mixing(nem_sim* s, int32_t r, const uint8_t* colour, int32_t ncol, int32_t B, int64_t* counts,
+               double* index) {
+  if (!s || r < 0 || r >= s->R || !colour || ncol < 1 || ncol > 255 || B < 1 || B > 1024) return NEM_E_INVAL;
+  if (!s->has_state[r]) { s->err = "state of this replica was never set"; return NEM_E_STATE; }
+  const int n = (int)s->n[r];
+  for (int i = 0; i < n; ++i)
+    if (colour[i] >= ncol) { s->err = "colour out of range"; return NEM_E_INVAL; }
+  const size_t nb = (size_t)B * B * ncol;
+  if (nb > s->mix_cap) {
+    if (s->g_mix) HIPCHK(hipFree(s->g_mix));
+    s->g_mix = nullptr; s->mix_cap = 0;
+    HIPCHK(hipMalloc((void**)&s->g_mix, sizeof(unsigned long long) * nb));
+    s->mix_cap = nb;
+  }
+  uint8_t* d_col = (uint8_t*)s->stage;  // n bytes of the 9 n double staging area
+  HIPCHK(hipMemcpyAsync(d_col, colour, (size_t)n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipMemsetAsync(s->g_mix, 0, sizeof(unsigned long long) * nb, s->stream));
+  SortArgs a = sort_args(s, nullptr);
+  launch_colour_counts(a, r, n, d_col, ncol, B, s->g_mix, s->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<unsigned long long> h(nb);
+  HIPCHK(hipMemcpyAsync(h.data(), s->g_mix, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  rc = status_from_flags(s, f[0]);
+  if (counts)
+    for (size_t k = 0; k < nb; ++k) counts[k] = (int64_t)h[k];
+  if (index) {
+    // intensity of segregation: sum over bins and colours of N_b (phi_cb - phi_c)^2,
+    // over its value sum_c N phi_c (1 - phi_c) for fully segregated colours
+    std::vector<double> Nc(ncol, 0.0);
+    double N = 0.0;
+    for (size_t b = 0; b < (size_t)B * B; ++b)
+      for (int c = 0; c < ncol; ++c) { Nc[c] += (double)h[b * ncol + c]; N += (double)h[b * ncol + c]; }
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < ncol; ++c) den += Nc[c] * (1.0 - Nc[c] / N);
+    for (size_t b = 0; b < (size_t)B * B; ++b) {
+      double Nb = 0.0;
+      for (int c = 0; c < ncol; ++c) Nb += (double)h[b * ncol + c];
+      if (Nb <= 0.0) continue;
+      for (int c = 0; c < ncol; ++c) {
+        const double d = (double)h[b * ncol + c] - Nb * Nc[c] / N;
+        num += d * d / Nb;
+      }
+    }
+    *index = den > 0.0 ? 1.0 - num / den : NAN;
+  }
+  return rc;
+}
+
 int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus) {
   if (!s || !n_plus || !n_minus) return NEM_E_INVAL;
   int rc = deposit_grid(s, r, M);
@@ -786,6 +865,7 @@ void nem_destroy(nem_sim* s) {
   drop_graphs(s);
   if (s->cap_stream) hipStreamDestroy(s->cap_stream);
   free_grid(s);
+  if (s->g_mix) hipFree(s->g_mix);
   free_snapshot(s);
   if (s->own && s->arena) hipFree(s->arena);
   delete s;

@@ -98,8 +98,10 @@ struct SortArgs {
   int* perm;             // [ntot]
   // unsorted staging copy of the persistent fields
   int* t_key; float2* t_off; float2* t_lo; float2* t_u; float2* t_q; float* t_drho; float2* t_acc; int* t_id;
+  int2* t_img;
   // persistent sorted fields
   float2* off; float2* offlo; float2* u; float2* q; float* drho; float2* acc; int* id; int* cell;
+  int2* img;             // periodic image of each particle: unwrapped r = r + img * L
   unsigned* flags;
   const unsigned* gate;  // run only when *gate != 0 (NULL: always)
   const float2* off_build;  // offsets at the last Verlet build (displacement checks)
@@ -116,6 +118,9 @@ void launch_rebin_key(const SortArgs& s, hipStream_t st);
 void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base, hipStream_t st);
 void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st);
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st);
+void launch_track(const SortArgs& s, int r, int n, int* inv, const int* ids, int nt, double* out, hipStream_t st);
+void launch_colour_counts(const SortArgs& s, int r, int n, const uint8_t* colour, int ncol, int B,
+                          unsigned long long* counts, hipStream_t st);
 void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* red, hipStream_t st);
 void launch_free_energy(int T, const StepArgs& a, double* fe, hipStream_t s);
 void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st);

@@ -183,7 +183,7 @@ __global__ void k_rows_by_id(SortArgs s, const float* src, float* dst, int w) {
 // then 4-byte words for the tail; every buffer is 4-byte sized and every
 // buffer longer than 16 bytes starts 16-byte aligned).
 struct CopySeg { const void* src; void* dst; int64_t bytes; };
-struct CopyList { CopySeg seg[12]; int n; };
+struct CopyList { CopySeg seg[14]; int n; };
 __global__ void k_copy_list(CopyList L) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,7 +238,7 @@ namespace nem_host {
 void free_snapshot(nem_sim* s) {
   for (auto& S : s->snap) {
     for (void* p : {(void*)S.off, (void*)S.offlo, (void*)S.u, (void*)S.q, (void*)S.acc, (void*)S.drho, (void*)S.id,
-                    (void*)S.cell, (void*)S.cell_start, (void*)S.umax})
+                    (void*)S.cell, (void*)S.img, (void*)S.cell_start, (void*)S.umax})
       if (p) hipFree(p);
     S = nem_sim::Snap();
   }
@@ -256,6 +256,7 @@ int take_snapshot(nem_sim* s, int i) {
     HIPCHK(hipMalloc((void**)&S.drho, sizeof(float) * N));
     HIPCHK(hipMalloc((void**)&S.id, sizeof(int) * N));
     HIPCHK(hipMalloc((void**)&S.cell, sizeof(int) * N));
+    HIPCHK(hipMalloc((void**)&S.img, sizeof(int2) * N));
     HIPCHK(hipMalloc((void**)&S.cell_start, sizeof(int) * (C + 1)));
     HIPCHK(hipMalloc((void**)&S.umax, sizeof(unsigned) * (s->R * UMAX_SLOTS + 1)));  // + rebin request
     S.alloc = true;
@@ -263,7 +264,11 @@ int take_snapshot(nem_sim* s, int i) {
   const int p = s->parity;
   CopyList cl;
   cl.n = 0;
-  auto add = [&](const void* src, void* dst, size_t bytes) { cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes}; };
+  bool full = false;
+  auto add = [&](const void* src, void* dst, size_t bytes) {
+    if (cl.n < (int)(sizeof(cl.seg) / sizeof(cl.seg[0]))) cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes};
+    else full = true;
+  };
   add(s->off[p], S.off, sizeof(float2) * N);
   add(s->offlo, S.offlo, sizeof(float2) * N);
   add(s->u, S.u, sizeof(float2) * N);
@@ -272,9 +277,11 @@ int take_snapshot(nem_sim* s, int i) {
   add(s->drho, S.drho, sizeof(float) * N);
   add(s->id, S.id, sizeof(int) * N);
   add(s->cell, S.cell, sizeof(int) * N);
+  add(s->img, S.img, sizeof(int2) * N);
   add(s->cell_start, S.cell_start, sizeof(int) * (C + 1));
   add(s->umax + (size_t)p * s->R * UMAX_SLOTS, S.umax, sizeof(unsigned) * s->R * UMAX_SLOTS);
   add(s->flags + 1, S.umax + s->R * UMAX_SLOTS, sizeof(unsigned));  // rebin request
+  if (full) { s->err = "snapshot copy list too long"; return NEM_E_INVAL; }
   hipLaunchKernelGGL(k_copy_list, dim3(1024), dim3(256), 0, s->stream, cl);
   HIPCHK(hipGetLastError());
   S.parity = p;
@@ -291,7 +298,11 @@ int restore_snapshot(nem_sim* s, int i) {
   const int p = S.parity;
   CopyList cl;
   cl.n = 0;
-  auto add = [&](const void* src, void* dst, size_t bytes) { cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes}; };
+  bool full = false;
+  auto add = [&](const void* src, void* dst, size_t bytes) {
+    if (cl.n < (int)(sizeof(cl.seg) / sizeof(cl.seg[0]))) cl.seg[cl.n++] = CopySeg{src, dst, (int64_t)bytes};
+    else full = true;
+  };
   add(S.off, s->off[p], sizeof(float2) * N);
   add(S.offlo, s->offlo, sizeof(float2) * N);
   add(S.u, s->u, sizeof(float2) * N);
@@ -300,11 +311,13 @@ int restore_snapshot(nem_sim* s, int i) {
   add(S.drho, s->drho, sizeof(float) * N);
   add(S.id, s->id, sizeof(int) * N);
   add(S.cell, s->cell, sizeof(int) * N);
+  add(S.img, s->img, sizeof(int2) * N);
   add(S.cell_start, s->cell_start, sizeof(int) * (C + 1));
   add(S.umax, s->umax + (size_t)p * s->R * UMAX_SLOTS, sizeof(unsigned) * s->R * UMAX_SLOTS);
   // keep the sticky error bits (flags[0]), restore the rebin request (flags[1]);
   // the Verlet list is not part of the snapshot: rebuild it
   add(S.umax + s->R * UMAX_SLOTS, s->flags + 1, sizeof(unsigned));
+  if (full) { s->err = "snapshot copy list too long"; return NEM_E_INVAL; }
   hipLaunchKernelGGL(k_copy_list, dim3(1024), dim3(256), 0, s->stream, cl);
   HIPCHK(hipGetLastError());
   launch_request_relist(s->flags, s->stream);

@@ -24,10 +24,11 @@ struct nem_sim {
   int nwork = 0, work_cap = 0;
   int *cell_start = nullptr, *count = nullptr, *cursor = nullptr, *perm = nullptr;
   int* t_key = nullptr; float2 *t_off = nullptr, *t_lo = nullptr, *t_u = nullptr, *t_q = nullptr;
-  float* t_drho = nullptr; float2* t_acc = nullptr; int* t_id = nullptr;
+  float* t_drho = nullptr; float2* t_acc = nullptr; int* t_id = nullptr; int2* t_img = nullptr;
   float2* off[2] = {nullptr, nullptr}; float2* offlo = nullptr; float2* u = nullptr;
   float2* q[2] = {nullptr, nullptr}; float* drho = nullptr; float2* acc = nullptr;
   int* id = nullptr; int* cell = nullptr;
+  int2* img = nullptr;
   float* V = nullptr; float4* bk = nullptr; float* dh = nullptr; float2* apart = nullptr;
   float* uv = nullptr; float2* pi = nullptr; float* P = nullptr; float* drhat = nullptr;
   unsigned* flags = nullptr; unsigned* umax = nullptr;
@@ -53,6 +54,8 @@ struct nem_sim {
   int gM = 0, gbins = 0;
   double* g_grid = nullptr; double2* g_z = nullptr; double2* g_w = nullptr;
   double* g_part = nullptr; double* g_E = nullptr; unsigned long long* g_cnt = nullptr;
+  // mixing histogram (B * B * ncol counters) and its capacity
+  unsigned long long* g_mix = nullptr; size_t mix_cap = 0;
   // learned stepping: feature output of pass B (NULL when not capturing) and
   // the device snapshot used to restart a macro step with fine steps
   float* feat = nullptr;
@@ -61,6 +64,7 @@ struct nem_sim {
     float2 *off = nullptr, *offlo = nullptr, *u = nullptr, *q = nullptr, *acc = nullptr;
     float* drho = nullptr;
     int *id = nullptr, *cell = nullptr, *cell_start = nullptr;
+    int2* img = nullptr;
     unsigned* umax = nullptr;  // R * UMAX_SLOTS max-speed slots, then the rebin request
     int parity = 0;
     std::vector<float> dt;

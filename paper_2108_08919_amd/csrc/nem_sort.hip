@@ -43,8 +43,11 @@ __global__ void k_ingest(SortArgs s, int r, const double* __restrict__ in, int n
     const double hdt = 0.5 * (double)R.dt;
     const double uhx = ux[i] + hdt * ax[i], uhy = uy[i] + hdt * ay[i];
     double xh = x[i] + hdt * uhx, yh = y[i] + hdt * uhy;
-    xh = xh - R.Ld * floor(xh / R.Ld); if (xh >= R.Ld) xh -= R.Ld; if (xh < 0.0) xh = 0.0;
-    yh = yh - R.Ld * floor(yh / R.Ld); if (yh >= R.Ld) yh -= R.Ld; if (yh < 0.0) yh = 0.0;
+    // wrap into [0, L), counting the periodic images taken off
+    double ix = floor(xh / R.Ld), iy = floor(yh / R.Ld);
+    xh = xh - R.Ld * ix; if (xh >= R.Ld) { xh -= R.Ld; ix += 1.0; } if (xh < 0.0) xh = 0.0;
+    yh = yh - R.Ld * iy; if (yh >= R.Ld) { yh -= R.Ld; iy += 1.0; } if (yh < 0.0) yh = 0.0;
+    if (!(fabs(ix) < 1e9 && fabs(iy) < 1e9)) { atomicOr(s.flags, ERR_RANGE); ix = 0.0; iy = 0.0; }
     int cx = (int)floor(xh / R.csd), cy = (int)floor(yh / R.csd);
     cx = min(max(cx, 0), R.nc - 1);
     cy = min(max(cy, 0), R.nc - 1);
@@ -63,6 +66,7 @@ __global__ void k_ingest(SortArgs s, int r, const double* __restrict__ in, int n
     s.t_drho[k] = (float)(rho[i] - (double)R.rho0);
     s.t_acc[k] = make_float2((float)ax[i], (float)ay[i]);
     s.t_id[k] = i;
+    s.t_img[k] = make_int2((int)ix, (int)iy);
     atomicAdd(&s.count[key], 1);
     atomicMax(&umax[r * UMAX_SLOTS + (i & (UMAX_SLOTS - 1))], __float_as_uint(sqrtf(uf.x * uf.x + uf.y * uf.y)));
   }
@@ -99,6 +103,10 @@ __global__ void k_rebin_key(SortArgs s) {
       l2 = (lo.y + sly) + e;
       nh.y = t + l2; nl.y = l2 - (nh.y - t);
     }
+    // crossing the periodic boundary changes the particle's image
+    int2 im = s.img[k];
+    if (cx + dx < 0) im.x -= 1; else if (cx + dx >= R.nc) im.x += 1;
+    if (cy + dy < 0) im.y -= 1; else if (cy + dy >= R.nc) im.y += 1;
     cx = (cx + dx + R.nc) % R.nc;
     cy = (cy + dy + R.nc) % R.nc;
     const int key = R.cell_base + cy * R.nc + cx;
@@ -110,6 +118,7 @@ __global__ void k_rebin_key(SortArgs s) {
     s.t_drho[k] = s.drho[k];
     s.t_acc[k] = s.acc[k];
     s.t_id[k] = s.id[k];
+    s.t_img[k] = im;
     atomicAdd(&s.count[key], 1);
   }
 }
@@ -191,6 +200,7 @@ __global__ void k_gather(SortArgs s, int k0, int n, int c0, int nc) {
     s.drho[k] = s.t_drho[src];
     s.acc[k] = s.t_acc[src];
     s.id[k] = s.t_id[src];
+    s.img[k] = s.t_img[src];
     s.cell[k] = s.t_key[src];
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
@@ -219,6 +229,27 @@ __global__ void k_request_relist(unsigned* flags) {
   if (blockIdx.x == 0 && threadIdx.x == 0) flags[2] = 1u;
 }
 
+// Position of sorted particle k at the integer time level,
+// r^n = r^{n+1/2} - u^{n+1/2} dt/2, relative to the box of its image (may lie
+// just outside [0, L) after the half-step back).
+__device__ inline void position_n(const SortArgs& s, const RepDev& R, int k, double& x, double& y) {
+#pragma clang fp contract(off)
+  const int c = s.cell[k] - R.cell_base;
+  const int cx = c % R.nc, cy = c / R.nc;
+  const float2 o = s.off[k], lo = s.offlo[k], uh = s.u[k];
+  const double hdt = 0.5 * (double)R.dt;
+  x = (double)cx * R.csd + ((double)o.x + (double)lo.x) - hdt * (double)uh.x;
+  y = (double)cy * R.csd + ((double)o.y + (double)lo.y) - hdt * (double)uh.y;
+}
+
+// The same wrapped into [0, L).
+__device__ inline void position_n_wrapped(const SortArgs& s, const RepDev& R, int k, double& x, double& y) {
+#pragma clang fp contract(off)
+  position_n(s, R, k, x, y);
+  x = x - R.Ld * floor(x / R.Ld); if (x >= R.Ld) x -= R.Ld;
+  y = y - R.Ld * floor(y / R.Ld); if (y >= R.Ld) y -= R.Ld;
+}
+
 // Sorted state of replica r -> FP64 arrays in id order at the integer time
 // level: r^n = r^{n+1/2} - u^{n+1/2} dt/2, u^n = u^{n+1/2} - a dt/2.
 __global__ void k_export(SortArgs s, int r, double* out, int n) {
@@ -228,16 +259,12 @@ __global__ void k_export(SortArgs s, int r, double* out, int n) {
     const int k = R.part_base + i;
     const int id = s.id[k];
     if (id < 0 || id >= n) { atomicOr(s.flags, ERR_RANGE); continue; }
-    const int c = s.cell[k] - R.cell_base;
-    const int cx = c % R.nc, cy = c / R.nc;
-    const float2 o = s.off[k], lo = s.offlo[k], uh = s.u[k], ac = s.acc[k], q = s.q[k];
+    const float2 uh = s.u[k], ac = s.acc[k], q = s.q[k];
     const double hdt = 0.5 * (double)R.dt;
     const double uxn = (double)uh.x - hdt * (double)ac.x;
     const double uyn = (double)uh.y - hdt * (double)ac.y;
-    double x = (double)cx * R.csd + ((double)o.x + (double)lo.x) - hdt * (double)uh.x;
-    double y = (double)cy * R.csd + ((double)o.y + (double)lo.y) - hdt * (double)uh.y;
-    x = x - R.Ld * floor(x / R.Ld); if (x >= R.Ld) x -= R.Ld;
-    y = y - R.Ld * floor(y / R.Ld); if (y >= R.Ld) y -= R.Ld;
+    double x, y;
+    position_n_wrapped(s, R, k, x, y);
     out[id] = x;
     out[(size_t)n + id] = y;
     out[2 * (size_t)n + id] = uxn;
@@ -247,6 +274,59 @@ __global__ void k_export(SortArgs s, int r, double* out, int n) {
     out[6 * (size_t)n + id] = (double)R.rho0 + (double)s.drho[k];
     out[7 * (size_t)n + id] = (double)ac.x;
     out[8 * (size_t)n + id] = (double)ac.y;
+  }
+}
+
+// Pathlines: inv[id] = sorted slot of every particle of replica r.
+__global__ void k_track_inv(SortArgs s, int r, int n, int* inv) {
+  const RepDev R = s.reps[r];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = R.part_base + i;
+    const int id = s.id[k];
+    if (id < 0 || id >= n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    inv[id] = k;
+  }
+}
+
+// Unwrapped integer-level positions of the particles ids[0..nt):
+// out[t] = x + img_x L, out[nt + t] = y + img_y L.
+__global__ void k_track(SortArgs s, int r, int n, const int* inv, const int* ids, int nt, double* out) {
+  const RepDev R = s.reps[r];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+#pragma clang fp contract(off)
+    const int id = ids[t];
+    const int k = (id >= 0 && id < n) ? inv[id] : -1;
+    if (k < R.part_base || k >= R.part_base + n) {
+      atomicOr(s.flags, ERR_RANGE);
+      out[t] = NAN; out[(size_t)nt + t] = NAN;
+      continue;
+    }
+    double x, y;
+    position_n(s, R, k, x, y);
+    const int2 im = s.img[k];
+    out[t] = x + (double)im.x * R.Ld;
+    out[(size_t)nt + t] = y + (double)im.y * R.Ld;
+  }
+}
+
+// Mixing: counts[(by * B + bx) * ncol + c] = particles of colour c (by id) in
+// bin (bx, by) of a B x B partition of the box, from the wrapped integer-level
+// positions, bx = floor(x B / L).
+__global__ void k_colour_counts(SortArgs s, int r, int n, const uint8_t* colour, int ncol, int B,
+                                unsigned long long* counts) {
+  const RepDev R = s.reps[r];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma clang fp contract(off)
+    const int k = R.part_base + i;
+    const int id = s.id[k];
+    if (id < 0 || id >= n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const int c = colour[id];
+    if (c >= ncol) { atomicOr(s.flags, ERR_RANGE); continue; }
+    double x, y;
+    position_n_wrapped(s, R, k, x, y);
+    const int bx = min(max((int)floor(x * (double)B / R.Ld), 0), B - 1);
+    const int by = min(max((int)floor(y * (double)B / R.Ld), 0), B - 1);
+    atomicAdd(&counts[((size_t)by * B + bx) * ncol + c], 1ull);
   }
 }
 
@@ -336,6 +416,16 @@ void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* re
 }
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_export, dim3(grid_for(n)), dim3(256), 0, st, s, r, out, n);
+}
+
+void launch_track(const SortArgs& s, int r, int n, int* inv, const int* ids, int nt, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_track_inv, dim3(grid_for(n)), dim3(256), 0, st, s, r, n, inv);
+  hipLaunchKernelGGL(k_track, dim3(grid_for(nt)), dim3(256), 0, st, s, r, n, (const int*)inv, ids, nt, out);
+}
+
+void launch_colour_counts(const SortArgs& s, int r, int n, const uint8_t* colour, int ncol, int B,
+                          unsigned long long* counts, hipStream_t st) {
+  hipLaunchKernelGGL(k_colour_counts, dim3(grid_for(n)), dim3(256), 0, st, s, r, n, colour, ncol, B, counts);
 }
 
 }  // namespace nem

@@ -34,3 +34,13 @@ def test_table_averages_over_seeds():
 
 def test_grid_side_is_a_power_of_two_covering_the_box():
     assert [sweep._pow2_at_least(v) for v in (5.0, 64.0, 65.0, 128.0, 384.0)] == [8, 64, 128, 128, 512]
+
+
+def test_lagrangian_quadrant_colours_match_the_oracle_reading():
+    import numpy as np
+    from oracle import lagrangian as lg
+    from paper_2108_08919_amd import lagrangian
+    rng = np.random.default_rng(2)
+    L = 40.0
+    x, y = rng.uniform(-L, 2 * L, 1000), rng.uniform(-L, 2 * L, 1000)
+    assert np.array_equal(lagrangian.quadrant_colour(x, y, L), lg.quadrant_colour(np.mod(x, L), np.mod(y, L), L))
