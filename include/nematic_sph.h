@@ -65,11 +65,13 @@ typedef struct nem_params {
   double gamma_eos;  /* EoS exponent (7) */
   double beta;       /* density filter coefficient (1) */
   double c0_factor;  /* c0 = c0_factor * max |u^{n+1/2}| (10) */
-  double skin;       /* cell side >= 3h + skin; rebinning when a particle leaves its cell by skin/2 */
+  double skin;       /* cell side >= kappa h + skin; rebinning when a particle leaves its cell by skin/2 */
   int32_t form;      /* 0: B-corrected momentum of Eq. sphMomentum; 1: conservative pair forces */
   int32_t elastic;   /* 0: stress of Eq. mainstress; 1: also the lambda terms of Eq. elasticstress */
   int32_t apd;       /* 1: artificial particle displacement (Eq. APD) */
-  int32_t reserved;
+  int32_t kernel;    /* smoothing kernel: 0 quintic spline of support kappa h = 3h (Eq. quintic);
+                        1 Wendland C2, W = 7/(4 pi h^2) (1 - q/2)^4 (1 + 2q), q = r/h < 2 (kappa = 2).
+                        Every replica of one simulation uses the same form, elastic and kernel. */
 } nem_params;
 
 /* FP64 global reductions at the current integer time level. */

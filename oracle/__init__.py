@@ -22,7 +22,7 @@ class OrcParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K", "zeta",
                  "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
-               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search")]
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search", "kernel")]
 
 
 class OrcState(C.Structure):
@@ -44,8 +44,9 @@ def lib():
             _b.build()
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
-        L.orc_W.restype = C.c_double; L.orc_W.argtypes = [C.c_double, C.c_double]
-        L.orc_dWdr.restype = C.c_double; L.orc_dWdr.argtypes = [C.c_double, C.c_double]
+        L.orc_W.restype = C.c_double; L.orc_W.argtypes = [C.c_int32, C.c_double, C.c_double]
+        L.orc_dWdr.restype = C.c_double; L.orc_dWdr.argtypes = [C.c_int32, C.c_double, C.c_double]
+        L.orc_kappa.restype = C.c_double; L.orc_kappa.argtypes = [C.c_int32]
         L.orc_eos.restype = C.c_double; L.orc_eos.argtypes = [C.c_double] * 4
         L.orc_neighbors.restype = C.c_int64
         L.orc_neighbors.argtypes = [C.POINTER(OrcParams), C.c_int64, dp, dp, C.c_int32, C.c_int32,
@@ -81,15 +82,19 @@ def make_params(p, search: int = 0) -> OrcParams:
     return OrcParams(L=p.L, dx=p.dx, h=p.h, rho0=p.rho0, eta=p.eta, Gamma=p.Gamma, lam=p.lam,
                      A=p.A, B=p.B, C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos,
                      beta=p.beta, c0_factor=p.c0_factor, skin=p.skin, form=p.form,
-                     elastic=p.elastic, apd=p.apd, search=search)
+                     elastic=p.elastic, apd=p.apd, search=search, kernel=getattr(p, "kernel", 0))
 
 
-def W(h: float, r: float) -> float:
-    return lib().orc_W(h, r)
+def W(h: float, r: float, kernel: int = 0) -> float:
+    return lib().orc_W(kernel, h, r)
 
 
-def dWdr(h: float, r: float) -> float:
-    return lib().orc_dWdr(h, r)
+def dWdr(h: float, r: float, kernel: int = 0) -> float:
+    return lib().orc_dWdr(kernel, h, r)
+
+
+def kappa(kernel: int = 0) -> float:
+    return lib().orc_kappa(kernel)
 
 
 def eos(rho, rho0, c0, gamma_eos):

@@ -30,10 +30,20 @@
 
 /* ------------------------------------------------------------------ kernel */
 
-/* Eq. quintic with kappa = 3 and the 2D normalisation a_d = 7/(478 pi h^2);
- * b = r/h. */
-double orc_W(double h, double r) {
+/* Support radius of the kernel in units of h. */
+double orc_kappa(int32_t kernel) { return kernel == 1 ? 2.0 : 3.0; }
+
+/* kernel 0: Eq. quintic with kappa = 3 and the 2D normalisation
+ * a_d = 7/(478 pi h^2); kernel 1: the Wendland C2 function of support 2h,
+ * a_d (1 - q/2)^4 (1 + 2q) with a_d = 7/(4 pi h^2). b = q = r/h. */
+double orc_W(int32_t kernel, double h, double r) {
   double b = r / h;
+  if (kernel == 1) {
+    if (b >= 2.0) return 0.0;
+    double ad = 7.0 / (4.0 * PI * h * h);
+    double t = 1.0 - 0.5 * b;
+    return ad * t * t * t * t * (1.0 + 2.0 * b);
+  }
   if (b >= 3.0) return 0.0;
   double ad = 7.0 / (478.0 * PI * h * h);
   double t3 = 3.0 - b, t2 = 2.0 - b, t1 = 1.0 - b;
@@ -43,9 +53,17 @@ double orc_W(double h, double r) {
   return ad * s;
 }
 
-/* dW/dr of Eq. quintic. */
-double orc_dWdr(double h, double r) {
+/* dW/dr of either kernel (for Wendland C2 the product rule on
+ * t^4 (1 + 2q), t = 1 - q/2, then dq/dr = 1/h). */
+double orc_dWdr(int32_t kernel, double h, double r) {
   double b = r / h;
+  if (kernel == 1) {
+    if (b >= 2.0) return 0.0;
+    double ad = 7.0 / (4.0 * PI * h * h);
+    double t = 1.0 - 0.5 * b;
+    double dq = 4.0 * t * t * t * (-0.5) * (1.0 + 2.0 * b) + t * t * t * t * 2.0;
+    return ad * dq / h;
+  }
   if (b >= 3.0) return 0.0;
   double ad = 7.0 / (478.0 * PI * h * h);
   double t3 = 3.0 - b, t2 = 2.0 - b, t1 = 1.0 - b;
@@ -175,11 +193,12 @@ static int cells_build(cells* c, int64_t n, const double* x, const double* y, do
 static void cells_free(cells* c) { free(c->start); free(c->idx); free(c->cx); free(c->cy); }
 
 /* Neighbour predicate (reading of Eq. quintic's support): j != i with
- * 0 < |r_ij| < 3h under the minimum-image convention. W(3h) = 0, so pairs at
- * exactly 3h carry no weight either way. */
+ * 0 < |r_ij| < kappa h (3h for the quintic spline, 2h for Wendland C2) under
+ * the minimum-image convention. W(kappa h) = 0, so pairs at exactly kappa h
+ * carry no weight either way. */
 static int build_nlist(const orc_params* p, int64_t n, const double* x, const double* y,
                        int brute, nlist* nl) {
-  const double L = p->L, R = 3.0 * p->h, R2 = R * R;
+  const double L = p->L, R = orc_kappa(p->kernel) * p->h, R2 = R * R;
   memset(nl, 0, sizeof(*nl));
   nl->n = n;
   nl->ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
@@ -243,13 +262,14 @@ static int build_nlist(const orc_params* p, int64_t n, const double* x, const do
  * displaced by d in {-1,0,1} from i's cell (periodic),
  *   rx = fl32( fl32(offx_i - offx_j) + fl32(-d_x) * fl32(cs) ),
  *   r2 = fl32( fl32(rx*rx) + fl32(ry*ry) ),
- * accepted when 0 < r2 < fl32((3h)^2). No fused multiply-add anywhere. */
+ * accepted when 0 < r2 < fl32((kappa h)^2). No fused multiply-add anywhere. */
 static int64_t fp32_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,
                               int nc, int64_t* row_ptr, int32_t* col, int64_t cap) {
   if (nc < 3) return -1;
   const double csd = p->L / nc;
   const float csf = (float)csd;
-  const float R2f = (float)((3.0 * p->h) * (3.0 * p->h));
+  const double Rs = orc_kappa(p->kernel) * p->h;
+  const float R2f = (float)(Rs * Rs);
   int32_t* cx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
   int32_t* cy = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
   float* ox = (float*)malloc(sizeof(float) * (size_t)(n + 1));
@@ -308,12 +328,12 @@ int64_t orc_neighbors(const orc_params* p, int64_t n, const double* x, const dou
 
 /* Eq. sphSum: V_i = 1 / sum_j W_ij, the sum including the particle itself. */
 static void op_volume(const orc_params* p, const nlist* nl, double* V) {
-  const double W0 = orc_W(p->h, 0.0);
+  const double W0 = orc_W(p->kernel, p->h, 0.0);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nl->n; ++i) {
     double s = W0;
     for (int64_t k = nl->ptr[i]; k < nl->ptr[i + 1]; ++k)
-      s += orc_W(p->h, hypot(nl->rx[k], nl->ry[k]));
+      s += orc_W(p->kernel, p->h, hypot(nl->rx[k], nl->ry[k]));
     V[i] = 1.0 / s;
   }
 }
@@ -328,7 +348,7 @@ static int op_correction(const orc_params* p, const nlist* nl, const double* V, 
     double a[4] = {0, 0, 0, 0};
     for (int64_t k = nl->ptr[i]; k < nl->ptr[i + 1]; ++k) {
       double rx = nl->rx[k], ry = nl->ry[k], r = hypot(rx, ry);
-      double dW = orc_dWdr(p->h, r);
+      double dW = orc_dWdr(p->kernel, p->h, r);
       double gx = dW * rx / r, gy = dW * ry / r;   /* grad_i W_ij */
       double Vj = V[nl->j[k]];
       double jx = -rx, jy = -ry;                   /* r_ji */
@@ -375,7 +395,7 @@ int orc_operators(const orc_params* p, int64_t n, const double* x, const double*
         int32_t j = nl.j[k];
         double rx = nl.rx[k], ry = nl.ry[k], r = hypot(rx, ry);
         double gx, gy;
-        corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->h, r), &gx, &gy);
+        corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->kernel, p->h, r), &gx, &gy);
         sx += V[j] * (f[j] - f[i]) * gx;
         sy += V[j] * (f[j] - f[i]) * gy;
         sl += V[j] * (f[i] - f[j]) * (rx * gx + ry * gy) / (r * r);
@@ -410,7 +430,7 @@ static void work_free(work* w) {
 static int eval_rates(const orc_params* p, const orc_state* s, const double* xh, const double* yh,
                       const double* uxh, const double* uyh, work* w) {
   const int64_t n = s->n;
-  const double h = p->h, W0 = orc_W(h, 0.0), dt = p->dt;
+  const double h = p->h, W0 = orc_W(p->kernel, h, 0.0), dt = p->dt;
   const double m = p->rho0 * p->dx * p->dx;   /* particle mass, constant */
   memset(w, 0, sizeof(*w));
   int rc = build_nlist(p, n, xh, yh, p->search == 1, &w->nl);
@@ -443,7 +463,7 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
     double G[4] = {0, 0, 0, 0}, kk = 0;
     for (int64_t q = nl->ptr[i]; q < nl->ptr[i + 1]; ++q) {
       int32_t j = nl->j[q];
-      double rx = nl->rx[q], ry = nl->ry[q], r = hypot(rx, ry), dW = orc_dWdr(h, r);
+      double rx = nl->rx[q], ry = nl->ry[q], r = hypot(rx, ry), dW = orc_dWdr(p->kernel, h, r);
       double du[2] = {uxh[j] - uxh[i], uyh[j] - uyh[i]};
       if (p->form == 0) {
         double gx, gy;
@@ -470,7 +490,7 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
   for (int64_t i = 0; i < n; ++i) {
     double num = 0.0, den = W0;
     for (int64_t q = nl->ptr[i]; q < nl->ptr[i + 1]; ++q) {
-      double Wij = orc_W(h, hypot(nl->rx[q], nl->ry[q]));
+      double Wij = orc_W(p->kernel, h, hypot(nl->rx[q], nl->ry[q]));
       num += (w->rh[i] - w->rh[nl->j[q]]) * Wij;
       den += Wij;
     }
@@ -499,7 +519,7 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
       int32_t j = nl->j[q];
       const double* Qj = s->q + 4 * j;
       double rx = nl->rx[q], ry = nl->ry[q], r = hypot(rx, ry), gx, gy;
-      corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(h, r), &gx, &gy);
+      corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->kernel, h, r), &gx, &gy);
       double rg = (rx * gx + ry * gy) / (r * r);
       for (int c = 0; c < 4; ++c) {
         gq[2 * c] += V[j] * (Qj[c] - Qi[c]) * gx;
@@ -541,7 +561,7 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
       int32_t j = nl->j[q];
       const double* Qj = s->q + 4 * j;
       double rx = nl->rx[q], ry = nl->ry[q], r = hypot(rx, ry);
-      double dW = orc_dWdr(h, r), Wij = orc_W(h, r);
+      double dW = orc_dWdr(p->kernel, h, r), Wij = orc_W(p->kernel, h, r);
       double rj = w->rhat[j], Pj = w->pr[j] / (rj * rj);
       double uij[2] = {uxh[i] - uxh[j], uyh[i] - uyh[j]};
       double ur = (uij[0] * rx + uij[1] * ry) / (r * r);
@@ -605,7 +625,7 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
 }
 
 static int check_params(const orc_params* p) {
-  if (!(p->L > 2.0 * 3.0 * p->h) || !(p->h > 0) || !(p->dx > 0) || !(p->rho0 > 0) || !(p->dt > 0))
+  if (!(p->L > 2.0 * orc_kappa(p->kernel) * p->h) || !(p->h > 0) || !(p->dx > 0) || !(p->rho0 > 0) || !(p->dt > 0))
     return -1;
   return 0;
 }
@@ -717,7 +737,7 @@ int orc_diagnostics(const orc_params* p, const orc_state* s, orc_diag* out) {
       int32_t j = nl.j[q];
       const double* Qj = s->q + 4 * j;
       double rx = nl.rx[q], ry = nl.ry[q], r = hypot(rx, ry), gx, gy;
-      corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(h, r), &gx, &gy);
+      corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->kernel, h, r), &gx, &gy);
       double rg = (rx * gx + ry * gy) / (r * r);
       for (int c = 0; c < 4; ++c) {
         gq[2 * c] += V[j] * (Qj[c] - Qi[c]) * gx;
@@ -747,11 +767,11 @@ int orc_diagnostics(const orc_params* p, const orc_state* s, orc_diag* out) {
 }
 
 /* Shepard interpolation onto grid nodes: f_g = sum_j f_j W_gj / sum_j W_gj over
- * particles within 3h of the node (minimum image). Nodes with no particle
- * within the support get 0. */
+ * particles within the kernel support kappa h of the node (minimum image).
+ * Nodes with no particle within the support get 0. */
 int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* y,
                 int32_t nf, const double* const* fields, int32_t M, double* out) {
-  const double L = p->L, h = p->h, R = 3.0 * h;
+  const double L = p->L, h = p->h, R = orc_kappa(p->kernel) * h;
   int nc = (int)floor(L / R);
   if (nc < 3) nc = 1;
   cells c;
@@ -775,7 +795,7 @@ int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* y
           double dx = minimg(gx - x[j], L), dy = minimg(gy - y[j], L);
           double r = hypot(dx, dy);
           if (r >= R) continue;
-          double Wg = orc_W(h, r);
+          double Wg = orc_W(p->kernel, h, r);
           den += Wg;
           for (int f = 0; f < nf && f < 16; ++f) num[f] += fields[f][j] * Wg;
         }

@@ -25,6 +25,7 @@ typedef struct orc_params {
   int32_t elastic; /* 1 adds the lambda terms of Eq. elasticstress */
   int32_t apd;     /* artificial particle displacement (Eq. APD) */
   int32_t search;  /* 0 cell list, 1 brute force O(N^2) */
+  int32_t kernel;  /* 0 quintic spline (Eq. quintic, support 3h), 1 Wendland C2 (support 2h) */
 } orc_params;
 
 typedef struct orc_state {
@@ -45,9 +46,11 @@ typedef struct orc_diag {
   double c0_last;     /* sound speed used by the last step */
 } orc_diag;
 
-/* Quintic spline (Eq. quintic, 2D normalisation) and its radial derivative. */
-double orc_W(double h, double r);
-double orc_dWdr(double h, double r);
+/* Smoothing kernel (0 quintic spline of Eq. quintic, 1 Wendland C2; 2D
+ * normalisation), its radial derivative and its support in units of h. */
+double orc_W(int32_t kernel, double h, double r);
+double orc_dWdr(int32_t kernel, double h, double r);
+double orc_kappa(int32_t kernel);
 
 /* Neighbour lists in CSR by particle index, columns ascending.
  * mode 0: FP64 minimum image, cell list;  1: FP64 minimum image, brute force;

@@ -36,7 +36,10 @@ struct Layout {
   }
 };
 
-int cells_per_side(const nem_params& p) { return (int)std::floor(p.L / (3.0 * p.h + p.skin)); }
+// support radius of the smoothing kernel in units of h
+double kappa(const nem_params& p) { return p.kernel == 1 ? 2.0 : 3.0; }
+
+int cells_per_side(const nem_params& p) { return (int)std::floor(p.L / (kappa(p) * p.h + p.skin)); }
 
 int check_params(const nem_params& p, int64_t n, std::string& why) {
   auto bad = [&](const char* m) { why = m; return NEM_E_INVAL; };
@@ -44,7 +47,8 @@ int check_params(const nem_params& p, int64_t n, std::string& why) {
   if (!(p.skin >= 0)) return bad("skin must be >= 0");
   if (!(p.gamma_eos > 0)) return bad("gamma_eos must be positive");
   if (n < 1 || n > (int64_t)1 << 30) return bad("particle count out of range");
-  if (cells_per_side(p) < 3) return bad("box side must hold three cells of side >= 3h + skin");
+  if (p.kernel != 0 && p.kernel != 1) return bad("kernel must be 0 (quintic spline) or 1 (Wendland C2)");
+  if (cells_per_side(p) < 3) return bad("box side must hold three cells of side >= kappa h + skin");
   if (p.form != 0 && p.form != 1) return bad("form must be 0 or 1");
   if (p.elastic != 0 && p.elastic != 1) return bad("elastic must be 0 or 1");
   if (p.form == 1 && p.elastic == 1) return bad("the conservative form has no elastic lambda terms on the GPU");
@@ -64,9 +68,16 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   R.csd = csd; R.Ld = p.L;
   R.cs = (float)csd; R.cs_lo = (float)(csd - (double)R.cs);
   R.h = (float)p.h; R.hinv = (float)(1.0 / p.h);
-  R.R2 = (float)((3.0 * p.h) * (3.0 * p.h));
-  const double a2 = 7.0 / (478.0 * M_PI * p.h * p.h);
-  R.a2 = (float)a2; R.W0 = (float)(66.0 * a2); R.dWc = (float)(-5.0 * a2 / p.h);
+  const double rs = kappa(p) * p.h;  // support radius
+  R.R2 = (float)(rs * rs);
+  R.kern = p.kernel;
+  if (p.kernel == 1) {
+    const double a2 = 7.0 / (4.0 * M_PI * p.h * p.h);
+    R.a2 = (float)a2; R.W0 = (float)a2; R.dWc = (float)(-5.0 * a2 / (p.h * p.h));
+  } else {
+    const double a2 = 7.0 / (478.0 * M_PI * p.h * p.h);
+    R.a2 = (float)a2; R.W0 = (float)(66.0 * a2); R.dWc = (float)(-5.0 * a2 / p.h);
+  }
   R.skin_half = (float)(0.5 * p.skin);
   R.rho0 = (float)p.rho0; R.eta = (float)p.eta; R.Gamma = (float)p.Gamma; R.lam = (float)p.lam;
   R.A = (float)p.A; R.B = (float)p.B; R.C = (float)p.C; R.K = (float)p.K; R.zeta = (float)p.zeta;
@@ -74,7 +85,7 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   R.c0_factor = (float)p.c0_factor; R.mass = (float)(p.rho0 * p.dx * p.dx); R.inv_rho0 = (float)(1.0 / p.rho0);
   R.elastic = p.elastic; R.apd = p.apd;
   const double delta = 0.1 * p.h;  // Verlet skin
-  R.R2v = (float)((3.0 * p.h + delta) * (3.0 * p.h + delta));
+  R.R2v = (float)((rs + delta) * (rs + delta));
   R.disp2 = (float)((0.45 * delta) * (0.45 * delta));
   return R;
 }
@@ -148,6 +159,11 @@ int sizes_for(const nem_params* p, const int64_t* n, int R, Sizes& s, std::strin
   for (int r = 0; r < R; ++r) {
     int rc = check_params(p[r], n[r], why);
     if (rc) return rc;
+    // one launch per pass serves every replica: the compiled variant is shared
+    if (p[r].form != p[0].form || p[r].elastic != p[0].elastic || p[r].kernel != p[0].kernel) {
+      why = "replicas of one simulation must share form, elastic and kernel";
+      return NEM_E_INVAL;
+    }
     const int nc = cells_per_side(p[r]);
     s.ntot += n[r];
     s.ncells += (int64_t)nc * nc;
@@ -271,7 +287,7 @@ struct Timed {
 // Enqueue one step (rebin if requested, step-begin, passes A-D) on stream st
 // for the current parity.
 int enqueue_step(nem_sim* s, hipStream_t st) {
-  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic};
+  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic, s->hp[0].kernel};
   {
     Timed t(s, 0);
     SortArgs a = sort_args(s, s->flags + 1);
@@ -357,7 +373,7 @@ int deposit_grid(nem_sim* s, int r, int M) {
   launch_int_offsets(a, s->t_off, s->stream);
   StepArgs sa = step_args(s);
   sa.off_cur = s->t_off;
-  launch_deposit(s->T, sa, r, M, s->g_grid, s->stream);
+  launch_deposit(s->T, s->hp[r].kernel, sa, r, M, s->g_grid, s->stream);
   HIPCHK(hipGetLastError());
   return NEM_OK;
 }
@@ -600,9 +616,9 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {
   launch_int_offsets(a, s->t_off, s->stream);
   StepArgs sa = step_args(s);
   sa.off_cur = s->t_off;
-  const PassCfg cfg{s->T, 1, 1, 0, 0};
+  const PassCfg cfg{s->T, 1, 1, 0, 0, s->hp[0].kernel};
   if (!launch_pass(1, cfg, sa, s->stream)) return NEM_E_INVAL;
-  launch_free_energy(s->T, sa, s->fe, s->stream);
+  launch_free_energy(s->T, s->hp[0].kernel, sa, s->fe, s->stream);
   launch_reduce(a, r, (int)s->n[r], s->fe, s->red, s->stream);
   HIPCHK(hipGetLastError());
   double h[8];

@@ -30,16 +30,18 @@ struct RepDev {
   int tiles_x, tiles_y, tile_base, form;
   float cs, cs_lo; // cell side as a float pair (cs + cs_lo = L/nc to ~1e-14 relative)
   float h, hinv;
-  float R2;        // fl32((3h)^2): pair accepted when 0 < r^2 < R2
-  float a2;        // 7 / (478 pi h^2)
-  float W0;        // W(0) = 66 a2
-  float dWc;       // dW/dr = dWc (t3^4 - 6 t2^4 + 15 t1^4), dWc = -5 a2 / h
+  float R2;        // fl32((kappa h)^2), kappa = 3 (quintic) or 2 (Wendland C2): pair accepted when 0 < r^2 < R2
+  float a2;        // normalisation: 7 / (478 pi h^2) (quintic), 7 / (4 pi h^2) (Wendland C2)
+  float W0;        // W(0): 66 a2 (quintic), a2 (Wendland C2)
+  float dWc;       // quintic: dW/dr = dWc (t3^4 - 6 t2^4 + 15 t1^4), dWc = -5 a2 / h;
+                   // Wendland C2: (dW/dr)/r = dWc (1 - q/2)^3, dWc = -5 a2 / h^2
   float skin_half, rho0, eta, Gamma;
   float lam, A, C, K;
   float zeta, dt, gamma_eos, beta;
   float c0_factor, mass, inv_rho0, B;
   int elastic, apd;
-  float R2v;       // Verlet list radius: fl32((3h + delta)^2), delta = 0.1 h
+  int kern;        // smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
+  float R2v;       // Verlet list radius: fl32((kappa h + delta)^2), delta = 0.1 h
   float disp2;     // rebuild the Verlet list when a particle moved more than 0.45 delta: (0.45 delta)^2
   double csd, Ld;
 };
@@ -85,7 +87,7 @@ struct StepArgs {
 };
 
 // Kernel variant of the pair passes.
-struct PassCfg { int T, LPP, COMP, FORM, EL; };
+struct PassCfg { int T, LPP, COMP, FORM, EL, KERN; };
 
 // Arguments of the binning, ingest, export and reduction kernels.
 struct SortArgs {
@@ -122,9 +124,9 @@ void launch_track(const SortArgs& s, int r, int n, int* inv, const int* ids, int
 void launch_colour_counts(const SortArgs& s, int r, int n, const uint8_t* colour, int ncol, int B,
                           unsigned long long* counts, hipStream_t st);
 void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* red, hipStream_t st);
-void launch_free_energy(int T, const StepArgs& a, double* fe, hipStream_t s);
+void launch_free_energy(int T, int kern, const StepArgs& a, double* fe, hipStream_t s);
 void launch_int_offsets(const SortArgs& s, float2* out, hipStream_t st);
-void launch_deposit(int T, const StepArgs& a, int rep, int M, double* grid, hipStream_t s);
+void launch_deposit(int T, int kern, const StepArgs& a, int rep, int M, double* grid, hipStream_t s);
 void launch_fft2(const double* grid, double2* z, double2* w, int M, int logM, hipStream_t s);
 void launch_shells(const double2* Z, int M, int nbins, double* part, double* E, hipStream_t s);
 void launch_vort_correlation(const double2* W, int M, int logM, double L, double2* z, double2* w, double* axes,

@@ -20,15 +20,15 @@
 namespace nem {
 
 // --------------------------------------------------------------- deposit
-template <int T>
+template <int T, int KERN>
 __global__ __launch_bounds__(WG) void k_deposit(const StepArgs a, int rep_only, int M, double* grid) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float4 s_f[MP];   // ux, uy, qxx, qxy at the integer level
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, blockIdx.x, L, R, rep)) return;
   if (rep != rep_only) return;
   const int ni = L.hdr[0], nj = L.hdr[1], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(WG) void k_deposit(const StepArgs a, int rep_only, 
         float rx, ry, r2;
         pair_accept(ox, oy, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2);
         if (!(r2 < R.R2)) continue;
-        const float w = (r2 > 0.0f) ? quintic_W(R, r2) : R.W0;
+        const float w = (r2 > 0.0f) ? kernel_w<KERN>(R, r2) : R.W0;
         const float4 f = s_f[j];
         den.add(w); fx.fma(f.x, w); fy.fma(f.y, w); fa.fma(f.z, w); fb.fma(f.w, w);
       }
@@ -192,10 +192,15 @@ __global__ void k_winding(const double* grid, int M, unsigned long long* counts)
 }
 
 // -------------------------------------------------------------- launchers
-void launch_deposit(int T, const StepArgs& a, int rep, int M, double* grid, hipStream_t s) {
+void launch_deposit(int T, int kern, const StepArgs& a, int rep, int M, double* grid, hipStream_t s) {
   const dim3 grid_(a.nwork), block(WG);
-  if (T == 8) hipLaunchKernelGGL((k_deposit<8>), grid_, block, 0, s, a, rep, M, grid);
-  else hipLaunchKernelGGL((k_deposit<4>), grid_, block, 0, s, a, rep, M, grid);
+  if (kern == 1) {
+    if (T == 8) hipLaunchKernelGGL((k_deposit<8, 1>), grid_, block, 0, s, a, rep, M, grid);
+    else hipLaunchKernelGGL((k_deposit<4, 1>), grid_, block, 0, s, a, rep, M, grid);
+  } else {
+    if (T == 8) hipLaunchKernelGGL((k_deposit<8, 0>), grid_, block, 0, s, a, rep, M, grid);
+    else hipLaunchKernelGGL((k_deposit<4, 0>), grid_, block, 0, s, a, rep, M, grid);
+  }
 }
 
 // |omega^(k)|^2 of the vorticity omega = d uy/dx - d ux/dy from the 2D FFT

@@ -1,4 +1,4 @@
-// nem_pair.h -- tile staging, neighbour predicate, quintic kernel and
+// nem_pair.h -- tile staging, neighbour predicate, smoothing kernels and
 // compensated sums used by every pair pass (gfx950, wave64).
 #pragma once
 #include "nem_dev.h"
@@ -8,10 +8,15 @@ namespace nem {
 // Tile geometry for a tile side of T cells. A workgroup stages the T x T
 // interior cells of its tile plus a one-cell periodic halo into LDS; interior
 // cells come first so that interior particles occupy LDS slots [0, nin).
-template <int T>
+// LDS particle capacity per staged cell: 24 for the quintic spline's cells
+// (side >= 3h + skin = 4 dx, 16 particles on the lattice), 10 for Wendland C2's
+// (side >= 2h + skin = 2.7 dx, 7.3 on the lattice), small enough that five
+// workgroups of the 8 x 8 tile fit in one CU's LDS. A tile holding more sets
+// ERR_OVERFLOW.
+template <int T, int KERN = 0>
 struct TileCfg {
   static constexpr int NSC = (T + 2) * (T + 2);
-  static constexpr int MAXP = NSC * 24;  // 1.5x the lattice fill of 16 per cell
+  static constexpr int MAXP = NSC * (KERN == 1 ? 10 : 24);
 };
 
 template <int T>
@@ -107,43 +112,62 @@ __device__ __forceinline__ bool pair_accept(float oix, float oiy, float ojx, flo
   return (r2 > 0.0f) & (r2 < R2);
 }
 
-// Quintic spline of support 3h (2D): W and F = (dW/dr)/r, so that
-// grad_i W_ij = F r_ij.
+// Smoothing kernels of support kappa h (2D), selected at compile time:
+//   KERN 0: quintic spline, kappa = 3 (Eq. quintic; the paper's kernel),
+//   KERN 1: Wendland C2, kappa = 2, W = a2 (1 - q/2)^4 (1 + 2q), a2 = 7/(4 pi h^2).
+// Each returns W and F = (dW/dr)/r, so that grad_i W_ij = F r_ij.
 // r2 is positive and far above the FP32 denormal range for every accepted pair
 // (particles never come within 1e-19 of each other), so the hardware
 // reciprocal square root is used without the denormal rescaling of rsqrtf.
 struct KW { float rinv, r, W, F; };
-__device__ __forceinline__ KW quintic(const RepDev& R, float r2) {
+template <int KERN>
+__device__ __forceinline__ KW kernel_wf(const RepDev& R, float r2) {
   KW k;
   k.rinv = __builtin_amdgcn_rsqf(r2);
   k.r = r2 * k.rinv;
   const float b = k.r * R.hinv;
-  const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
-  const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
-  const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
-  const float P4 = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34));
-  const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
-  k.W = R.a2 * P5;
-  k.F = R.dWc * P4 * k.rinv;
+  if constexpr (KERN == 0) {
+    const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
+    const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
+    const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
+    const float P4 = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34));
+    const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
+    k.W = R.a2 * P5;
+    k.F = R.dWc * P4 * k.rinv;   // dW/dr = dWc P4
+  } else {
+    // dW/dr = -5 a2 q (1 - q/2)^3 / h, so F = dWc (1 - q/2)^3 with dWc = -5 a2 / h^2
+    const float t = fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f);
+    const float t2 = t * t, t3 = t2 * t;
+    k.W = R.a2 * (t2 * t2) * fmaf(2.0f, b, 1.0f);
+    k.F = R.dWc * t3;
+  }
   return k;
 }
 
 // W only, also returning 1/r and r.
-__device__ __forceinline__ float quintic_Wr(const RepDev& R, float r2, float& rinv, float& r) {
+template <int KERN>
+__device__ __forceinline__ float kernel_wr(const RepDev& R, float r2, float& rinv, float& r) {
   rinv = __builtin_amdgcn_rsqf(r2);
   r = r2 * rinv;
   const float b = r * R.hinv;
-  const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
-  const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
-  const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
-  const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
-  return R.a2 * P5;
+  if constexpr (KERN == 0) {
+    const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
+    const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
+    const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
+    const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
+    return R.a2 * P5;
+  } else {
+    const float t = fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f);
+    const float t2 = t * t;
+    return R.a2 * (t2 * t2) * fmaf(2.0f, b, 1.0f);
+  }
 }
 
 // Same without the derivative (passes that need W only).
-__device__ __forceinline__ float quintic_W(const RepDev& R, float r2) {
+template <int KERN>
+__device__ __forceinline__ float kernel_w(const RepDev& R, float r2) {
   float rinv, r;
-  return quintic_Wr(R, r2, rinv, r);
+  return kernel_wr<KERN>(R, r2, rinv, r);
 }
 
 // A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: Kahan summation over
@@ -193,12 +217,12 @@ __device__ __forceinline__ void flag(unsigned* flags, unsigned bit) { atomicOr(f
 
 // Common prologue: set up the tile, check LDS capacity. Returns false when the
 // workgroup has nothing to do (uniform across the workgroup).
-template <int T>
+template <int T, int KERN = 0>
 __device__ __forceinline__ bool tile_begin(const StepArgs& a, int w, TileLDS<T>& L, RepDev& R, int& rep) {
   if (w >= a.nwork) return false;
   rep = tile_setup<T>(a, w, L, R);
   const int S = L.cstart[L.hdr[3]];
-  if (S > TileCfg<T>::MAXP) {
+  if (S > TileCfg<T, KERN>::MAXP) {
     if (threadIdx.x == 0) flag(a.flags, ERR_OVERFLOW);
     return false;
   }

@@ -93,15 +93,15 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
 constexpr int CELL_MAX = 48;
 constexpr unsigned long long MASK48 = (1ull << 48) - 1ull;
 
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  __shared__ float2 s_off[TileCfg<T>::MAXP];
+  __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
   __shared__ unsigned long long s_mask[9 * WG];  // lane-private, cell-major
-  static_assert(TileCfg<T>::MAXP <= 4096, "LDS slot must fit 12 bits");
+  static_assert(TileCfg<T, KERN>::MAXP <= 4096, "LDS slot must fit 12 bits");
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
@@ -165,7 +165,7 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
       float rx, ry, r2;
       pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2);
       float rinv, r;
-      sw.add(quintic_Wr(R, r2, rinv, r));
+      sw.add(kernel_wr<KERN>(R, r2, rinv, r));
       const float r3 = rinv * rinv * rinv;
       sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
       const uint32_t e = (uint32_t)j | (hi & 0xF000u);
@@ -195,7 +195,7 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 
 // The step's neighbour list of one particle under construction: accepted pairs
 // are summed (V, APD geometry) and appended as 16-bit entries.
-template <int COMP>
+template <int COMP, int KERN>
 struct ExactSink {
   Acc<COMP> sw, sx3, sy3, sr;
   int kept;
@@ -208,7 +208,7 @@ struct ExactSink {
   }
   __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
     float rinv, r;
-    sw.add(quintic_Wr(R, r2, rinv, r));
+    sw.add(kernel_wr<KERN>(R, r2, rinv, r));
     const float r3 = rinv * rinv * rinv;
     sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
     if (kept < KMAX) {
@@ -232,14 +232,14 @@ struct ExactSink {
 // Build: candidate search with the Verlet radius (masks as in pass A), then one
 // walk over the Verlet pairs in cell order that writes the Verlet list and
 // feeds the pairs passing the exact predicate to the step's list.
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  __shared__ float2 s_off[TileCfg<T>::MAXP];
+  __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
   __shared__ unsigned long long s_mask[9 * WG];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
@@ -283,7 +283,7 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
-    ExactSink<COMP> out;
+    ExactSink<COMP, KERN> out;
     out.init(a, g);
     int c = -1;
     unsigned long long m = 0ull, x = 0ull;
@@ -314,13 +314,13 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
 }
 
 // Walk: the Verlet pairs of each particle through the exact predicate.
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  __shared__ float2 s_off[TileCfg<T>::MAXP];
+  __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) s_off[t] = a.off_cur[staged_global<T>(a, L, t)];
@@ -334,7 +334,7 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     const float2 oi = s_off[p];
     const int vk = min(a.vcnt[g], KMAX);
-    ExactSink<COMP> out;
+    ExactSink<COMP, KERN> out;
     out.init(a, g);
     const uint32_t* src = a.vl + g;
     for (int k = 0; k < vk; k += 2) {
@@ -355,10 +355,10 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------------ pass B
-template <int T, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL, int KERN>
 __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float2 s_u[MP];
   __shared__ float2 s_q[MP];
@@ -366,7 +366,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
   __shared__ float s_rho[FORM == 1 ? MP : 1];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -412,7 +412,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        const KW k = quintic(R, r2);
+        const KW k = kernel_wf<KERN>(R, r2);
         const float Vj = s_V[j];
         const float2 uj = s_u[j], qj = s_q[j];
         const float c = Vj * k.F;              // V_j W'(r)/r
@@ -533,15 +533,15 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------------ pass C
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float s_dh[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -575,7 +575,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        sd.fma(s_dh[j], quintic_W(R, r2));
+        sd.fma(s_dh[j], kernel_w<KERN>(R, r2));
       }, [&]() { sd.end_cell(); });
     }
     const float tot = wave_sum(sd.value(), lpp);
@@ -599,10 +599,10 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------------ pass D
-template <int T, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL, int KERN>
 __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float s_V[MP];
   __shared__ float s_P[MP];
@@ -610,7 +610,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __shared__ float s_wmax[WG / 64];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, w, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -648,7 +648,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        const KW k = quintic(R, r2);
+        const KW k = kernel_wf<KERN>(R, r2);
         const float c = (FORM == 0) ? s_V[j] * k.F : k.F;
         const float f = (Pi + s_P[j]) * c;
         Px.fma(f, rx); Py.fma(f, ry);
@@ -752,16 +752,16 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
 //   F_i    = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 - K/2 Q:lapQ]
 //   F_grad = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 + K/2 sum_abc (d_c Q_ab)^2]
 // (trQ^3 = 0 in 2D). Runs after pass A on the integer-level offsets.
-template <int T>
+template <int T, int KERN>
 __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float2 s_q[MP];
   __shared__ float s_V[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, blockIdx.x, L, R, rep)) return;
   const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     each_listed(a.nl, a.ntot, g, min(a.ncnt[g], KMAX), 1, 0, [&](uint32_t e) {
       int j; float rx, ry, r2;
       listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-      const KW k = quintic(R, r2);
+      const KW k = kernel_wf<KERN>(R, r2);
       const float c = s_V[j] * k.F, cx = c * rx, cy = c * ry;
       const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
       Sxx.add(txx); Sxy.add(txy); Syy.add(tyy);
@@ -820,10 +820,15 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
   }
 }
 
-void launch_free_energy(int T, const StepArgs& a, double* fe, hipStream_t s) {
+void launch_free_energy(int T, int kern, const StepArgs& a, double* fe, hipStream_t s) {
   const dim3 grid(a.nwork), block(WG);
-  if (T == 8) hipLaunchKernelGGL((k_free_energy<8>), grid, block, 0, s, a, fe);
-  else hipLaunchKernelGGL((k_free_energy<4>), grid, block, 0, s, a, fe);
+  if (kern == 1) {
+    if (T == 8) hipLaunchKernelGGL((k_free_energy<8, 1>), grid, block, 0, s, a, fe);
+    else hipLaunchKernelGGL((k_free_energy<4, 1>), grid, block, 0, s, a, fe);
+  } else {
+    if (T == 8) hipLaunchKernelGGL((k_free_energy<8, 0>), grid, block, 0, s, a, fe);
+    else hipLaunchKernelGGL((k_free_energy<4, 0>), grid, block, 0, s, a, fe);
+  }
 }
 
 // ---------------------------------------------------------- neighbour export
@@ -880,104 +885,116 @@ __global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* s
 // ---------------------------------------------------------------- kernels
 // One workgroup per tile, or fewer workgroups looping over the tiles
 // (persistent launch: StepArgs::grid > 0).
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __global__ __launch_bounds__(WG) void k_pass_a(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a<T, COMP>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a<T, COMP, KERN>(a, w); __syncthreads(); }
 }
 // Gated on the rebuild flag of this step (flags[3], set by the step-begin
 // kernel): exactly one of the two runs its tiles, the other exits at once.
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __global__ __launch_bounds__(WG) void k_pass_a_build(const StepArgs a) {
   if (a.flags[3] == 0u) return;
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_build<T, COMP>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_build<T, COMP, KERN>(a, w); __syncthreads(); }
 }
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __global__ __launch_bounds__(WG) void k_pass_a_walk(const StepArgs a) {
   if (a.flags[3] != 0u) return;
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_walk<T, COMP>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_a_walk<T, COMP, KERN>(a, w); __syncthreads(); }
 }
 
 // Occupancy targets (waves per SIMD) of the pair passes: more resident waves
 // hide the LDS and list latency in each pair's dependency chain; the targets
 // are the largest that compile without register spills for the variant.
-template <int T, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL, int KERN>
 struct Waves {
-  static constexpr int B = (T == 4 && (COMP == 0 || (COMP == 1 && FORM == 0))) ? 5 : 1;
-  static constexpr int D = (T == 4 && EL == 0) ? 8 : 1;
+  static constexpr int B = ((T == 4 || KERN == 1) && (COMP == 0 || (COMP == 1 && FORM == 0))) ? 5 : 1;
+  static constexpr int D = ((T == 4 || KERN == 1) && EL == 0) ? 8 : 1;
 };
 
-template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL>::B)))
+template <int T, int COMP, int FORM, int EL, int KERN>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL, KERN>::B)))
 void k_pass_b(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL, KERN>(a, w); __syncthreads(); }
 }
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP, KERN>(a, w); __syncthreads(); }
 }
-template <int T, int COMP, int FORM, int EL>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL>::D)))
+template <int T, int COMP, int FORM, int EL, int KERN>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL, KERN>::D)))
 void k_pass_d(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL, KERN>(a, w); __syncthreads(); }
 }
 
 // ------------------------------------------------------------- dispatch
-template <int T, int COMP, int FORM, int EL>
+template <int T, int COMP, int FORM, int EL, int KERN>
 static void launch4(int pass, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.grid > 0 ? std::min(a.grid, a.nwork) : a.nwork), block(WG);
   switch (pass) {
-    case 1: hipLaunchKernelGGL((k_pass_a<T, COMP>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pass_c<T, COMP>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass_a<T, COMP, KERN>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL, KERN>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pass_c<T, COMP, KERN>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL, KERN>), grid, block, 0, s, a); break;
   }
 }
 
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 static bool launch_phys(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
-  if (c.FORM == 0 && c.EL == 0) { launch4<T, COMP, 0, 0>(pass, a, s); return true; }
-  if (c.FORM == 1 && c.EL == 0) { launch4<T, COMP, 1, 0>(pass, a, s); return true; }
-  if (c.FORM == 0 && c.EL == 1) { launch4<T, COMP, 0, 1>(pass, a, s); return true; }
+  if (c.FORM == 0 && c.EL == 0) { launch4<T, COMP, 0, 0, KERN>(pass, a, s); return true; }
+  if (c.FORM == 1 && c.EL == 0) { launch4<T, COMP, 1, 0, KERN>(pass, a, s); return true; }
+  if (c.FORM == 0 && c.EL == 1) { launch4<T, COMP, 0, 1, KERN>(pass, a, s); return true; }
   return false;
 }
 
-template <int T>
+template <int T, int KERN>
 static bool launch_comp(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
   switch (c.COMP) {
-    case 0: return launch_phys<T, 0>(pass, c, a, s);
-    case 1: return launch_phys<T, 1>(pass, c, a, s);
-    case 2: return launch_phys<T, 2>(pass, c, a, s);
+    case 0: return launch_phys<T, 0, KERN>(pass, c, a, s);
+    case 1: return launch_phys<T, 1, KERN>(pass, c, a, s);
+    case 2: return launch_phys<T, 2, KERN>(pass, c, a, s);
   }
   return false;
 }
 
-template <int T, int COMP>
+template <int T, int COMP, int KERN>
 static void launch_verlet(const StepArgs& a, hipStream_t s) {
   const int full = a.grid > 0 ? std::min(a.grid, a.nwork) : a.nwork;
   // the build runs rarely: a persistent grid keeps the skipped launch short
-  hipLaunchKernelGGL((k_pass_a_build<T, COMP>), dim3(std::min(full, 2048)), dim3(WG), 0, s, a);
-  hipLaunchKernelGGL((k_pass_a_walk<T, COMP>), dim3(full), dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_pass_a_build<T, COMP, KERN>), dim3(std::min(full, 2048)), dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_pass_a_walk<T, COMP, KERN>), dim3(full), dim3(WG), 0, s, a);
+}
+
+template <int KERN>
+static bool launch_verlet_k(const PassCfg& c, const StepArgs& a, hipStream_t s) {
+  switch (c.COMP * 2 + (c.T == 8 ? 1 : 0)) {
+    case 0: launch_verlet<4, 0, KERN>(a, s); return true;
+    case 1: launch_verlet<8, 0, KERN>(a, s); return true;
+    case 2: launch_verlet<4, 1, KERN>(a, s); return true;
+    case 3: launch_verlet<8, 1, KERN>(a, s); return true;
+    case 4: launch_verlet<4, 2, KERN>(a, s); return true;
+    case 5: launch_verlet<8, 2, KERN>(a, s); return true;
+  }
+  return false;
 }
 
 // Pass A of a step: Verlet build (when flagged) or walk.
 bool launch_pass_a_verlet(const PassCfg& c, const StepArgs& a, hipStream_t s) {
   if (c.T != 4 && c.T != 8) return false;
-  switch (c.COMP * 2 + (c.T == 8 ? 1 : 0)) {
-    case 0: launch_verlet<4, 0>(a, s); return true;
-    case 1: launch_verlet<8, 0>(a, s); return true;
-    case 2: launch_verlet<4, 1>(a, s); return true;
-    case 3: launch_verlet<8, 1>(a, s); return true;
-    case 4: launch_verlet<4, 2>(a, s); return true;
-    case 5: launch_verlet<8, 2>(a, s); return true;
-  }
+  if (c.KERN == 0) return launch_verlet_k<0>(c, a, s);
+  if (c.KERN == 1) return launch_verlet_k<1>(c, a, s);
   return false;
 }
 
 // Tiles of 4 or 8 cells; lanes per particle (1, 2, 4) is a runtime argument.
 bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
   if (c.LPP != 1 && c.LPP != 2 && c.LPP != 4) return false;
-  if (c.T == 4) return launch_comp<4>(pass, c, a, s);
-  if (c.T == 8) return launch_comp<8>(pass, c, a, s);
+  if (c.KERN == 0) {
+    if (c.T == 4) return launch_comp<4, 0>(pass, c, a, s);
+    if (c.T == 8) return launch_comp<8, 0>(pass, c, a, s);
+  } else if (c.KERN == 1) {
+    if (c.T == 4) return launch_comp<4, 1>(pass, c, a, s);
+    if (c.T == 8) return launch_comp<8, 1>(pass, c, a, s);
+  }
   return false;
 }
 

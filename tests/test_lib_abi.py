@@ -48,3 +48,16 @@ def test_host_only_calls():
         P.nem_arena_bytes([p.replace(form=1, elastic=1)], [4096])
     with pytest.raises(P.NemError):
         P.nem_arena_bytes([p], [0])
+
+
+def test_replicas_must_share_the_compiled_variant():
+    """One launch per pass serves every replica: form, elastic and kernel must
+    agree across replicas, and the kernel must be 0 or 1 (host-side check)."""
+    import paper_2108_08919_amd as P
+    import workloads as wl
+    p0 = wl.Params(L=32.0)
+    for ps in ([p0, p0.replace(kernel=1)], [p0, p0.replace(form=1)], [p0, p0.replace(elastic=1)],
+               [p0.replace(kernel=2)]):
+        with pytest.raises(P.NemError):
+            P.nem_arena_bytes(ps, [1024] * len(ps))
+    assert P.nem_arena_bytes([p0.replace(kernel=1)] * 2, [1024, 2048]) > 0

@@ -26,7 +26,7 @@ class Params:
     """Physical and numerical parameters of one box (one replica).
 
     Paper symbols: Table 2 (Gamma, lambda, A, B, C, K, mu, rho, zeta), Eq. quintic
-    (h, support 3h), Eq. sphEos (gamma = 7, c0 = 10 max|u|), Eq. densityCorrection
+    (h, support 3h; the Wendland C2 variant has support 2h), Eq. sphEos (gamma = 7, c0 = 10 max|u|), Eq. densityCorrection
     (beta = 1). dx is the lattice spacing, L the periodic box side.
     """
 
@@ -50,6 +50,7 @@ class Params:
     form: int = 0      # 0: corrected (B-contracted) momentum, 1: conservative pair forces
     elastic: int = 0   # 0: reduced stress (Eq. mainstress), 1: plus lambda terms of Eq. elasticstress
     apd: int = 1       # artificial particle displacement on/off
+    kernel: int = 0    # smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
