@@ -72,6 +72,11 @@ typedef struct nem_params {
   int32_t kernel;    /* smoothing kernel: 0 quintic spline of support kappa h = 3h (Eq. quintic);
                         1 Wendland C2, W = 7/(4 pi h^2) (1 - q/2)^4 (1 + 2q), q = r/h < 2 (kappa = 2).
                         Every replica of one simulation uses the same form, elastic and kernel. */
+  int32_t integrator;/* corrector (Sec. 3.1): 0 kick-drift-kick, u^{n+1} = u^{n+1/2} + a^{n+1/2} dt/2,
+                        r^{n+1} = r^{n+1/2} + u^{n+1} dt/2; 1 midpoint, u^{n+1} = u^n + a^{n+1/2} dt,
+                        r^{n+1} = r^n + u^{n+1/2} dt. Both add the APD shift to r and use the same
+                        predictor and density update. */
+  int32_t reserved;  /* 0 */
 } nem_params;
 
 /* FP64 global reductions at the current integer time level. */

@@ -22,7 +22,7 @@ class OrcParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K", "zeta",
                  "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
-               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search", "kernel")]
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search", "kernel", "integrator")]
 
 
 class OrcState(C.Structure):
@@ -82,7 +82,8 @@ def make_params(p, search: int = 0) -> OrcParams:
     return OrcParams(L=p.L, dx=p.dx, h=p.h, rho0=p.rho0, eta=p.eta, Gamma=p.Gamma, lam=p.lam,
                      A=p.A, B=p.B, C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos,
                      beta=p.beta, c0_factor=p.c0_factor, skin=p.skin, form=p.form,
-                     elastic=p.elastic, apd=p.apd, search=search, kernel=getattr(p, "kernel", 0))
+                     elastic=p.elastic, apd=p.apd, search=search, kernel=getattr(p, "kernel", 0),
+                     integrator=getattr(p, "integrator", 0))
 
 
 def W(h: float, r: float, kernel: int = 0) -> float:

@@ -652,15 +652,26 @@ int orc_step(const orc_params* p, orc_state* s, int64_t nsteps, orc_diag* info) 
     work w;
     int rc = eval_rates(p, s, xh, yh, uxh, uyh, &w);
     if (rc < 0) { work_free(&w); status = rc; break; }
-    /* corrector (reading of Sec. 3.1: kick-drift-kick):
-     * u^{n+1} = u^{n+1/2} + a^{n+1/2} dt/2, r^{n+1} = r^{n+1/2} + u^{n+1} dt/2,
-     * rho^{n+1} = rho_hat^{n+1/2} + k^{n+1/2} dt/2, then APD and wrap. */
+    /* corrector (reading of Sec. 3.1), kick-drift-kick:
+     * u^{n+1} = u^{n+1/2} + a^{n+1/2} dt/2, r^{n+1} = r^{n+1/2} + u^{n+1} dt/2;
+     * or the midpoint alternative: u^{n+1} = u^n + a^{n+1/2} dt,
+     * r^{n+1} = r^n + u^{n+1/2} dt. Both: rho^{n+1} = rho_hat^{n+1/2} + k^{n+1/2} dt/2,
+     * then APD and wrap. */
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < n; ++i) {
-      double ux = uxh[i] + 0.5 * w.ax[i] * dt, uy = uyh[i] + 0.5 * w.ay[i] * dt;
-      double x = xh[i] + 0.5 * ux * dt + w.dr[2 * i];
-      double y = yh[i] + 0.5 * uy * dt + w.dr[2 * i + 1];
+      double ux, uy, x, y;
+      if (p->integrator == 1) {
+        ux = s->ux[i] + w.ax[i] * dt;
+        uy = s->uy[i] + w.ay[i] * dt;
+        x = s->x[i] + uxh[i] * dt + w.dr[2 * i];
+        y = s->y[i] + uyh[i] * dt + w.dr[2 * i + 1];
+      } else {
+        ux = uxh[i] + 0.5 * w.ax[i] * dt;
+        uy = uyh[i] + 0.5 * w.ay[i] * dt;
+        x = xh[i] + 0.5 * ux * dt + w.dr[2 * i];
+        y = yh[i] + 0.5 * uy * dt + w.dr[2 * i + 1];
+      }
       s->ux[i] = ux; s->uy[i] = uy;
       s->x[i] = wrapc(x, L); s->y[i] = wrapc(y, L);
       s->rho[i] = w.rhat[i] + 0.5 * w.k[i] * dt;

@@ -26,6 +26,7 @@ typedef struct orc_params {
   int32_t apd;     /* artificial particle displacement (Eq. APD) */
   int32_t search;  /* 0 cell list, 1 brute force O(N^2) */
   int32_t kernel;  /* 0 quintic spline (Eq. quintic, support 3h), 1 Wendland C2 (support 2h) */
+  int32_t integrator; /* corrector: 0 kick-drift-kick, 1 midpoint (u^n + a dt, r^n + u^{n+1/2} dt) */
 } orc_params;
 
 typedef struct orc_state {

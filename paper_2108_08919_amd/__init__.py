@@ -50,7 +50,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
 class NemParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K",
                                           "zeta", "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
-               [(k, C.c_int32) for k in ("form", "elastic", "apd", "kernel")]
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "kernel", "integrator", "reserved")]
 
 
 class NemDiag(C.Structure):
@@ -160,7 +160,8 @@ def make_params(p) -> NemParams:
     """From workloads.Params (or any object with the same attribute names)."""
     return NemParams(L=p.L, dx=p.dx, h=p.h, rho0=p.rho0, eta=p.eta, Gamma=p.Gamma, lam=p.lam, A=p.A, B=p.B,
                      C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos, beta=p.beta,
-                     c0_factor=p.c0_factor, skin=p.skin, form=p.form, elastic=p.elastic, apd=p.apd, kernel=p.kernel)
+                     c0_factor=p.c0_factor, skin=p.skin, form=p.form, elastic=p.elastic, apd=p.apd, kernel=p.kernel,
+                     integrator=p.integrator, reserved=0)
 
 
 def _dp(a):

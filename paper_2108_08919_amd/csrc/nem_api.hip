@@ -48,6 +48,7 @@ int check_params(const nem_params& p, int64_t n, std::string& why) {
   if (!(p.gamma_eos > 0)) return bad("gamma_eos must be positive");
   if (n < 1 || n > (int64_t)1 << 30) return bad("particle count out of range");
   if (p.kernel != 0 && p.kernel != 1) return bad("kernel must be 0 (quintic spline) or 1 (Wendland C2)");
+  if (p.integrator != 0 && p.integrator != 1) return bad("integrator must be 0 (kick-drift-kick) or 1 (midpoint)");
   if (cells_per_side(p) < 3) return bad("box side must hold three cells of side >= kappa h + skin");
   if (p.form != 0 && p.form != 1) return bad("form must be 0 or 1");
   if (p.elastic != 0 && p.elastic != 1) return bad("elastic must be 0 or 1");
@@ -71,6 +72,7 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   const double rs = kappa(p) * p.h;  // support radius
   R.R2 = (float)(rs * rs);
   R.kern = p.kernel;
+  R.integ = p.integrator;
   if (p.kernel == 1) {
     const double a2 = 7.0 / (4.0 * M_PI * p.h * p.h);
     R.a2 = (float)a2; R.W0 = (float)a2; R.dWc = (float)(-5.0 * a2 / (p.h * p.h));

@@ -41,6 +41,7 @@ struct RepDev {
   float c0_factor, mass, inv_rho0, B;
   int elastic, apd;
   int kern;        // smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
+  int integ;       // corrector: 0 kick-drift-kick, 1 midpoint
   float R2v;       // Verlet list radius: fl32((kappa h + delta)^2), delta = 0.1 h
   float disp2;     // rebuild the Verlet list when a particle moved more than 0.45 delta: (0.45 delta)^2
   double csd, Ld;

@@ -690,7 +690,14 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       }
       const float2 uh = a.u[g];
       const float hdt = 0.5f * R.dt;
-      const float u1x = uh.x + hdt * ax, u1y = uh.y + hdt * ay;   // u^{n+1}
+      float u1x, u1y;                                              // u^{n+1}
+      if (R.integ == 0) {                                          // kick-drift-kick
+        u1x = uh.x + hdt * ax; u1y = uh.y + hdt * ay;
+      } else {                                                     // midpoint: u^n + a dt,
+        const float2 ap = a.acc[g];                                // u^n = u^{n+1/2} - a^{n-1/2} dt/2
+        u1x = (uh.x - hdt * ap.x) + R.dt * ax;
+        u1y = (uh.y - hdt * ap.y) + R.dt * ay;
+      }
       float drx = 0.f, dry = 0.f;
       const float4 ag = a.apdg[g];  // sum rx/r^3, sum ry/r^3, sum r, count
       if (R.apd && ag.w > 0.0f) {
@@ -699,8 +706,11 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
         drx = f * ag.x; dry = f * ag.y;
       }
       const float unx = u1x + hdt * ax, uny = u1y + hdt * ay;      // u^{n+3/2}
-      const float dispx = hdt * u1x + drx + hdt * unx;
-      const float dispy = hdt * u1y + dry + hdt * uny;
+      // r^{n+1} - r^{n+1/2}: u^{n+1} dt/2 (kick-drift-kick) or u^{n+1/2} dt/2
+      // (midpoint, r^n + u^{n+1/2} dt), then the next predictor's u^{n+3/2} dt/2
+      const float vdx = R.integ == 0 ? u1x : uh.x, vdy = R.integ == 0 ? u1y : uh.y;
+      const float dispx = hdt * vdx + drx + hdt * unx;
+      const float dispy = hdt * vdy + dry + hdt * uny;
       // compensated position update: (hi, lo) += disp
       const float2 lo = a.offlo[g];
       float2 nh, nl;

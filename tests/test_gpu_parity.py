@@ -266,3 +266,49 @@ def test_replicas_match_solo_runs():
         assert np.array_equal(ga[k], ha[k]), k
         assert np.array_equal(gb[k], hb[k]), k
     sim.close(); x1.close(); x2.close()
+
+
+@pytest.mark.parametrize("seed,opts", [(6, {}), (7, {"tile": 8, "lpp": 2})])
+def test_midpoint_corrector_ten_steps(seed, opts):
+    """The midpoint corrector (u^n + a dt, r^n + u^{n+1/2} dt) against the oracle."""
+    import paper_2108_08919_amd as P
+    keymap = {"tile": P.NEM_OPT_TILE, "lpp": P.NEM_OPT_LPP}
+    L = 40
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04, integrator=1)
+    s0 = random_state(L, seed, amp_u=2e-3)
+    s0["ax"] = 1e-3 * np.sin(2 * np.pi * s0["y"] / L)   # a nonzero a^{n-1/2} enters u^n
+    say("midpoint 10 steps", seed, opts)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10, {keymap[k]: v for k, v in opts.items()})
+    e = field_errors(g, o, s0, L)
+    check(e)
+    assert e["dQ"] < 1e-4 and e["drho"] < 1e-3
+    sim.close()
+
+
+def test_midpoint_second_order_on_gpu():
+    """Shear-wave decay: the GPU's midpoint corrector converges at second order
+    in dt, its kick-drift-kick at first order (both against exp(lambda t))."""
+    import math
+    L, m, A = 32, 8, 1e-6
+    x, y = wl.lattice(L)
+    n = x.size
+    k = 2 * math.pi * m / L
+    i = int(np.argmax(np.sin(k * y)))
+    st = dict(x=x, y=y, ux=A * np.sin(k * y), uy=np.zeros(n), qxx=np.ones(n), qxy=np.zeros(n), rho=np.ones(n),
+              ax=np.zeros(n), ay=np.zeros(n))
+    p0 = wl.Params(L=float(L), zeta=0.0, K=0.0, apd=0)
+    o = oracle.State(st)
+    oracle.step(p0.replace(dt=0.05), o, 1)
+    lam = o.fields()["ax"][i] / (A * math.sin(k * y[i]))
+    errs = {}
+    for integ in (0, 1):
+        e = []
+        for dt in (0.05, 0.025):
+            g, sim = gpu_run(p0.replace(dt=dt, integrator=integ), st, int(round(1.0 / dt)))
+            e.append(abs(g["ux"][i] / (A * math.sin(k * y[i])) - math.exp(lam)))
+            sim.close()
+        errs[integ] = e
+    print(errs, flush=True)
+    assert errs[0][0] / errs[0][1] == pytest.approx(2.0, rel=0.1)
+    assert errs[1][0] / errs[1][1] == pytest.approx(4.0, rel=0.1)

@@ -51,6 +51,7 @@ class Params:
     elastic: int = 0   # 0: reduced stress (Eq. mainstress), 1: plus lambda terms of Eq. elasticstress
     apd: int = 1       # artificial particle displacement on/off
     kernel: int = 0    # smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
+    integrator: int = 0  # corrector: 0 kick-drift-kick, 1 midpoint (u^n + a dt)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
