@@ -22,12 +22,12 @@ class OrcParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K", "zeta",
                  "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
-               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search", "kernel", "integrator")]
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "search", "kernel", "integrator", "q3d")]
 
 
 class OrcState(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.POINTER(C.c_double)) for k in
-                                     ("x", "y", "ux", "uy", "q", "rho", "ax", "ay")]
+                                     ("x", "y", "ux", "uy", "q", "rho", "ax", "ay", "qzz")]
 
 
 class OrcDiag(C.Structure):
@@ -54,6 +54,9 @@ def lib():
         L.orc_operators.restype = C.c_int
         L.orc_operators.argtypes = [C.POINTER(OrcParams), C.c_int64, dp, dp, dp, dp, dp, dp, dp]
         L.orc_corotation.restype = None; L.orc_corotation.argtypes = [C.c_double, dp, dp, dp]
+        L.orc_corotation3.restype = None; L.orc_corotation3.argtypes = [C.c_double, dp, dp, dp]
+        L.orc_molecular_field3.restype = None
+        L.orc_molecular_field3.argtypes = [C.POINTER(OrcParams), dp, dp, dp]
         L.orc_molecular_field.restype = None
         L.orc_molecular_field.argtypes = [C.POINTER(OrcParams), dp, dp, dp]
         L.orc_step.restype = C.c_int
@@ -83,7 +86,7 @@ def make_params(p, search: int = 0) -> OrcParams:
                      A=p.A, B=p.B, C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos,
                      beta=p.beta, c0_factor=p.c0_factor, skin=p.skin, form=p.form,
                      elastic=p.elastic, apd=p.apd, search=search, kernel=getattr(p, "kernel", 0),
-                     integrator=getattr(p, "integrator", 0))
+                     integrator=getattr(p, "integrator", 0), q3d=getattr(p, "q3d", 0))
 
 
 def W(h: float, r: float, kernel: int = 0) -> float:
@@ -122,15 +125,20 @@ class State:
             self.q[:, 2] = fields["qyx"]
         if "qyy" in fields:
             self.q[:, 3] = fields["qyy"]
+        # quasi-2D 3x3 Q: Qzz kept as its own component (None for the d = 2 reading)
+        self.qzz = f("qzz") if "qzz" in fields else None
 
     def c(self) -> OrcState:
         return OrcState(n=self.n, x=_dp(self.x), y=_dp(self.y), ux=_dp(self.ux), uy=_dp(self.uy),
-                        q=_dp(self.q), rho=_dp(self.rho), ax=_dp(self.ax), ay=_dp(self.ay))
+                        q=_dp(self.q), rho=_dp(self.rho), ax=_dp(self.ax), ay=_dp(self.ay), qzz=_dp(self.qzz))
 
     def fields(self) -> Dict[str, np.ndarray]:
-        return dict(x=self.x.copy(), y=self.y.copy(), ux=self.ux.copy(), uy=self.uy.copy(),
-                    qxx=self.q[:, 0].copy(), qxy=self.q[:, 1].copy(), qyx=self.q[:, 2].copy(),
-                    qyy=self.q[:, 3].copy(), rho=self.rho.copy(), ax=self.ax.copy(), ay=self.ay.copy())
+        out = dict(x=self.x.copy(), y=self.y.copy(), ux=self.ux.copy(), uy=self.uy.copy(),
+                   qxx=self.q[:, 0].copy(), qxy=self.q[:, 1].copy(), qyx=self.q[:, 2].copy(),
+                   qyy=self.q[:, 3].copy(), rho=self.rho.copy(), ax=self.ax.copy(), ay=self.ay.copy())
+        if self.qzz is not None:
+            out["qzz"] = self.qzz.copy()
+        return out
 
 
 def step(params, state: State, nsteps: int, search: int = 0) -> OrcDiag:
@@ -208,6 +216,24 @@ def corotation(lam: float, Q, G):
     S = np.zeros(4)
     lib().orc_corotation(lam, _dp(Q), _dp(G), _dp(S))
     return S.reshape(2, 2)
+
+
+def corotation3(lam: float, Q, G):
+    """Quasi-2D co-rotation (3x3 Q, I/3) for an in-plane 2x2 velocity gradient G."""
+    Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(9))
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(4))
+    S = np.zeros(9)
+    lib().orc_corotation3(lam, _dp(Q), _dp(G), _dp(S))
+    return S.reshape(3, 3)
+
+
+def molecular_field3(params, Q, lapQ):
+    Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(9))
+    lq = np.ascontiguousarray(np.asarray(lapQ, dtype=np.float64).reshape(9))
+    H = np.zeros(9)
+    cp = make_params(params)
+    lib().orc_molecular_field3(C.byref(cp), _dp(Q), _dp(lq), _dp(H))
+    return H.reshape(3, 3)
 
 
 def molecular_field(params, Q, lapQ):

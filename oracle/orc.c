@@ -126,6 +126,52 @@ void orc_molecular_field(const orc_params* p, const double* Q, const double* lap
     H[k] = -p->A * Q[k] + p->B * (Q2[k] - 0.5 * t * I[k]) - p->C * Q[k] * t + p->K * lapQ[k];
 }
 
+/* ------------------------------------------------------------ 3x3 algebra */
+/* Row-major 3x3, quasi-2D variant: the flow is in the plane (no u_z, no z
+ * dependence), Q is a full 3x3 tensor and the identity is I/3 as printed. */
+static void mm3(const double* a, const double* b, double* c) {
+  double r[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += a[3 * i + k] * b[3 * k + j];
+      r[3 * i + j] = s;
+    }
+  memcpy(c, r, sizeof(r));
+}
+static double tr3(const double* a) { return a[0] + a[4] + a[8]; }
+
+/* Eq. corotation as printed (D = Q + I/3), E and W of the in-plane G padded
+ * with zeros in the z row and column. */
+void orc_corotation3(double lam, const double* Q, const double* G, double* S) {
+  double G3[9] = {G[0], G[1], 0.0, G[2], G[3], 0.0, 0.0, 0.0, 0.0};
+  double E[9], W[9], D[9], P[9], M[9], t1[9], t2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      E[3 * i + j] = 0.5 * (G3[3 * i + j] + G3[3 * j + i]);
+      W[3 * i + j] = 0.5 * (G3[3 * i + j] - G3[3 * j + i]);
+      D[3 * i + j] = Q[3 * i + j] + (i == j ? 1.0 / 3.0 : 0.0);
+    }
+  for (int k = 0; k < 9; ++k) { P[k] = lam * E[k] + W[k]; M[k] = lam * E[k] - W[k]; }
+  mm3(P, D, t1);
+  mm3(D, M, t2);
+  double qg = 0.0;
+  for (int k = 0; k < 9; ++k) qg += Q[k] * G3[k];
+  for (int k = 0; k < 9; ++k) S[k] = t1[k] + t2[k] - 2.0 * lam * D[k] * qg;
+}
+
+/* Eq. molecularfielddis with I/3: H = -A Q + B (Q^2 - tr(Q^2) I/3) - C Q tr(Q^2) + K lapQ. */
+void orc_molecular_field3(const orc_params* p, const double* Q, const double* lapQ, double* H) {
+  double Q2[9];
+  mm3(Q, Q, Q2);
+  double t = tr3(Q2);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      int k = 3 * i + j;
+      H[k] = -p->A * Q[k] + p->B * (Q2[k] - (i == j ? t / 3.0 : 0.0)) - p->C * Q[k] * t + p->K * lapQ[k];
+    }
+}
+
 /* ------------------------------------------------------- neighbour lists */
 
 typedef struct nlist {
@@ -415,6 +461,7 @@ int orc_operators(const orc_params* p, int64_t n, const double* x, const double*
 typedef struct work {
   nlist nl;
   double *V, *Bt, *G, *k, *rh, *rhat, *pr, *gq, *lq, *H, *qn, *Pi, *ax, *ay, *dr;
+  double *qzn;   /* Qzz^{n+1} (quasi-2D variant only) */
   double c0;
   int singular;
 } work;
@@ -423,6 +470,7 @@ static void work_free(work* w) {
   nlist_free(&w->nl);
   free(w->V); free(w->Bt); free(w->G); free(w->k); free(w->rh); free(w->rhat); free(w->pr);
   free(w->gq); free(w->lq); free(w->H); free(w->qn); free(w->Pi); free(w->ax); free(w->ay); free(w->dr);
+  free(w->qzn);
 }
 
 /* Evaluate all rates of one step at the projected (half-step) configuration.
@@ -444,8 +492,9 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
   w->qn = malloc(sizeof(double) * 4 * N1); w->Pi = malloc(sizeof(double) * 4 * N1);
   w->ax = malloc(sizeof(double) * N1); w->ay = malloc(sizeof(double) * N1);
   w->dr = malloc(sizeof(double) * 2 * N1);
+  if (p->q3d) w->qzn = malloc(sizeof(double) * N1);
   if (!w->V || !w->Bt || !w->G || !w->k || !w->rh || !w->rhat || !w->pr || !w->gq || !w->lq ||
-      !w->H || !w->qn || !w->Pi || !w->ax || !w->ay || !w->dr)
+      !w->H || !w->qn || !w->Pi || !w->ax || !w->ay || !w->dr || (p->q3d && !w->qzn))
     return -3;
   const nlist* nl = &w->nl;
 
@@ -531,6 +580,34 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
     memcpy(w->gq + 8 * i, gq, sizeof(gq));
     memcpy(w->lq + 4 * i, lq, sizeof(lq));
     double H[4], S[4], mr[4];
+    if (p->q3d) {
+      /* quasi-2D: 3x3 Q with Qzz, the literal I/3 forms, then the rate is
+       * projected onto symmetric traceless 3x3 tensors */
+      double lz = 0.0;
+      for (int64_t q = nl->ptr[i]; q < nl->ptr[i + 1]; ++q) {
+        int32_t j = nl->j[q];
+        double rx = nl->rx[q], ry = nl->ry[q], r = hypot(rx, ry), gx, gy;
+        corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->kernel, h, r), &gx, &gy);
+        lz += V[j] * (s->qzz[i] - s->qzz[j]) * (rx * gx + ry * gy) / (r * r);
+      }
+      lz *= 2.0;
+      double Q3[9] = {Qi[0], Qi[1], 0.0, Qi[2], Qi[3], 0.0, 0.0, 0.0, s->qzz[i]};
+      double L3[9] = {lq[0], lq[1], 0.0, lq[2], lq[3], 0.0, 0.0, 0.0, lz};
+      double H3[9], S3[9], m3[9];
+      orc_molecular_field3(p, Q3, L3, H3);
+      orc_corotation3(p->lam, Q3, w->G + 4 * i, S3);
+      for (int c = 0; c < 9; ++c) m3[c] = S3[c] + p->Gamma * H3[c];
+      double t = tr3(m3) / 3.0, mp[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) mp[3 * a + b] = 0.5 * (m3[3 * a + b] + m3[3 * b + a]) - (a == b ? t : 0.0);
+      H[0] = H3[0]; H[1] = H3[1]; H[2] = H3[3]; H[3] = H3[4];
+      memcpy(w->H + 4 * i, H, sizeof(H));
+      w->qn[4 * i + 0] = Qi[0] + mp[0] * dt; w->qn[4 * i + 1] = Qi[1] + mp[1] * dt;
+      w->qn[4 * i + 2] = Qi[2] + mp[3] * dt; w->qn[4 * i + 3] = Qi[3] + mp[4] * dt;
+      w->qzn[i] = s->qzz[i] + mp[8] * dt;
+      for (int c = 0; c < 4; ++c) w->Pi[4 * i + c] = 0.0;
+      continue;
+    }
     orc_molecular_field(p, Qi, lq, H);
     orc_corotation(p->lam, Qi, w->G + 4 * i, S);
     for (int c = 0; c < 4; ++c) mr[c] = S[c] + p->Gamma * H[c];
@@ -627,11 +704,12 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
 static int check_params(const orc_params* p) {
   if (!(p->L > 2.0 * orc_kappa(p->kernel) * p->h) || !(p->h > 0) || !(p->dx > 0) || !(p->rho0 > 0) || !(p->dt > 0))
     return -1;
+  if (p->q3d && (p->form != 0 || p->elastic != 0)) return -1;  /* quasi-2D: corrected form, no lambda terms */
   return 0;
 }
 
 int orc_step(const orc_params* p, orc_state* s, int64_t nsteps, orc_diag* info) {
-  if (check_params(p)) return -1;
+  if (check_params(p) || (p->q3d && !s->qzz)) return -1;
   const int64_t n = s->n;
   const double dt = p->dt, L = p->L;
   size_t N1 = (size_t)n + 1;
@@ -677,6 +755,7 @@ int orc_step(const orc_params* p, orc_state* s, int64_t nsteps, orc_diag* info) 
       s->rho[i] = w.rhat[i] + 0.5 * w.k[i] * dt;
       s->ax[i] = w.ax[i]; s->ay[i] = w.ay[i];
       for (int c = 0; c < 4; ++c) s->q[4 * i + c] = w.qn[4 * i + c];
+      if (p->q3d) s->qzz[i] = w.qzn[i];
       if (!isfinite(ux) || !isfinite(uy) || !isfinite(s->rho[i]) || !isfinite(w.qn[4 * i]) || !isfinite(w.qn[4 * i + 1]))
         bad = 1;
     }
@@ -690,7 +769,7 @@ int orc_step(const orc_params* p, orc_state* s, int64_t nsteps, orc_diag* info) 
 
 int orc_step_fields(const orc_params* p, const orc_state* s, double* V, double* k,
                     double* rho_hat, double* pres, double* mrate, double* a, double* dr_apd) {
-  if (check_params(p)) return -1;
+  if (check_params(p) || (p->q3d && !s->qzz)) return -1;
   const int64_t n = s->n;
   const double dt = p->dt, L = p->L;
   size_t N1 = (size_t)n + 1;
@@ -729,6 +808,7 @@ int orc_step_fields(const orc_params* p, const orc_state* s, double* V, double* 
  * the discrete Laplacian (F = sum V [A/2 trQ^2 + B/3 trQ^3 + C/4 (trQ^2)^2]
  * - K/2 sum V Q:lapQ) and with the squared corrected gradient (F_grad). */
 int orc_diagnostics(const orc_params* p, const orc_state* s, orc_diag* out) {
+  if (p->q3d && !s->qzz) return -1;
   const int64_t n = s->n;
   const double m = p->rho0 * p->dx * p->dx, h = p->h;
   nlist nl;
@@ -756,19 +836,39 @@ int orc_diagnostics(const orc_params* p, const orc_state* s, orc_diag* out) {
         lq[c] += 2.0 * V[j] * (Qi[c] - Qj[c]) * rg;
       }
     }
-    double Q2[4], Q3[4];
-    mm(Qi, Qi, Q2); mm(Q2, Qi, Q3);
-    double t2 = tr2(Q2), t3 = tr2(Q3);
-    double bulk = 0.5 * p->A * t2 + p->B / 3.0 * t3 + 0.25 * p->C * t2 * t2;
-    double g2 = 0;
+    double t2, t3, g2 = 0, ql;
     for (int c = 0; c < 8; ++c) g2 += gq[c] * gq[c];
-    F += V[i] * (bulk - 0.5 * p->K * ddot(Qi, lq));
+    ql = ddot(Qi, lq);
+    if (p->q3d) {
+      /* quasi-2D: Qzz enters the invariants, its gradient and Laplacian */
+      double gz[2] = {0, 0}, lz = 0;
+      for (int64_t q = nl.ptr[i]; q < nl.ptr[i + 1]; ++q) {
+        int32_t j = nl.j[q];
+        double rx = nl.rx[q], ry = nl.ry[q], r = hypot(rx, ry), gx, gy;
+        corr_grad(Bt + 4 * i, rx, ry, r, orc_dWdr(p->kernel, h, r), &gx, &gy);
+        gz[0] += V[j] * (s->qzz[j] - s->qzz[i]) * gx;
+        gz[1] += V[j] * (s->qzz[j] - s->qzz[i]) * gy;
+        lz += 2.0 * V[j] * (s->qzz[i] - s->qzz[j]) * (rx * gx + ry * gy) / (r * r);
+      }
+      double Q3[9] = {Qi[0], Qi[1], 0.0, Qi[2], Qi[3], 0.0, 0.0, 0.0, s->qzz[i]}, A2[9], A3[9];
+      mm3(Q3, Q3, A2); mm3(A2, Q3, A3);
+      t2 = tr3(A2); t3 = tr3(A3);
+      g2 += gz[0] * gz[0] + gz[1] * gz[1];
+      ql += s->qzz[i] * lz;
+    } else {
+      double Q2[4], Q3[4];
+      mm(Qi, Qi, Q2); mm(Q2, Qi, Q3);
+      t2 = tr2(Q2); t3 = tr2(Q3);
+    }
+    double bulk = 0.5 * p->A * t2 + p->B / 3.0 * t3 + 0.25 * p->C * t2 * t2;
+    F += V[i] * (bulk - 0.5 * p->K * ql);
     Fg += V[i] * (bulk + 0.5 * p->K * g2);
     px += m * s->ux[i]; py += m * s->uy[i];
     double u2 = s->ux[i] * s->ux[i] + s->uy[i] * s->uy[i];
     ke += 0.5 * u2;
     if (sqrt(u2) > umax) umax = sqrt(u2);
-    if (fabs(Qi[0] + Qi[3]) > trq) trq = fabs(Qi[0] + Qi[3]);
+    double tq = Qi[0] + Qi[3] + (p->q3d ? s->qzz[i] : 0.0);
+    if (fabs(tq) > trq) trq = fabs(tq);
     if (fabs(Qi[1] - Qi[2]) > asym) asym = fabs(Qi[1] - Qi[2]);
   }
   out->px = px; out->py = py; out->ke = n > 0 ? ke / (double)n : 0.0;

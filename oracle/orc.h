@@ -27,6 +27,7 @@ typedef struct orc_params {
   int32_t search;  /* 0 cell list, 1 brute force O(N^2) */
   int32_t kernel;  /* 0 quintic spline (Eq. quintic, support 3h), 1 Wendland C2 (support 2h) */
   int32_t integrator; /* corrector: 0 kick-drift-kick, 1 midpoint (u^n + a dt, r^n + u^{n+1/2} dt) */
+  int32_t q3d;     /* 0: d = 2 (2x2 Q, I/2); 1: quasi-2D 3x3 Q with the printed I/3 (needs qzz) */
 } orc_params;
 
 typedef struct orc_state {
@@ -34,6 +35,7 @@ typedef struct orc_state {
   double *x, *y, *ux, *uy;
   double *q;       /* 4 per particle: Qxx, Qxy, Qyx, Qyy */
   double *rho, *ax, *ay;  /* density and a^{n-1/2} */
+  double *qzz;     /* Qzz per particle (quasi-2D 3x3 Q only; NULL otherwise) */
 } orc_state;
 
 typedef struct orc_diag {
@@ -52,6 +54,12 @@ typedef struct orc_diag {
 double orc_W(int32_t kernel, double h, double r);
 double orc_dWdr(int32_t kernel, double h, double r);
 double orc_kappa(int32_t kernel);
+
+/* Literal 3x3 forms (row-major, 9 entries) of Eq. corotation with I/3 and of
+ * Eq. molecularfielddis with I/3, for the quasi-2D variant; G is the 2x2
+ * in-plane velocity gradient (no z velocity, no z dependence). */
+void orc_corotation3(double lam, const double* Q, const double* G, double* S);
+void orc_molecular_field3(const orc_params* p, const double* Q, const double* lapQ, double* H);
 
 /* Neighbour lists in CSR by particle index, columns ascending.
  * mode 0: FP64 minimum image, cell list;  1: FP64 minimum image, brute force;

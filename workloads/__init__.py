@@ -52,6 +52,7 @@ class Params:
     apd: int = 1       # artificial particle displacement on/off
     kernel: int = 0    # smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
     integrator: int = 0  # corrector: 0 kick-drift-kick, 1 midpoint (u^n + a dt)
+    q3d: int = 0       # 0: 2x2 Q (d = 2); 1: quasi-2D 3x3 Q with the printed I/3
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -81,6 +82,14 @@ def director_angles(n: int, seed: int, kind: str) -> np.ndarray:
 def order_tensor(theta: np.ndarray, q0: float = 1.0):
     """(Qxx, Qxy) of the 2D order tensor for director angle theta, magnitude q0."""
     return q0 * np.cos(2.0 * theta), q0 * np.sin(2.0 * theta)
+
+
+def order_tensor3(theta: np.ndarray, q0: float = 1.0):
+    """(Qxx, Qxy, Qyy, Qzz) of the 3x3 order tensor Q = (3/2) q0 (n n - I/3) for
+    an in-plane director at angle theta (the d = 3 form of the paper's Q)."""
+    c, s = np.cos(theta), np.sin(theta)
+    return (1.5 * q0 * (c * c - 1.0 / 3.0), 1.5 * q0 * c * s, 1.5 * q0 * (s * s - 1.0 / 3.0),
+            np.full_like(theta, -0.5 * q0))
 
 
 def initial_state(n_side: int, dx: float, rho0: float, seed: int, kind: str, q0: float = 1.0) -> Dict[str, np.ndarray]:
