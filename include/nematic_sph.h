@@ -71,12 +71,17 @@ typedef struct nem_params {
   int32_t apd;       /* 1: artificial particle displacement (Eq. APD) */
   int32_t kernel;    /* smoothing kernel: 0 quintic spline of support kappa h = 3h (Eq. quintic);
                         1 Wendland C2, W = 7/(4 pi h^2) (1 - q/2)^4 (1 + 2q), q = r/h < 2 (kappa = 2).
-                        Every replica of one simulation uses the same form, elastic and kernel. */
+                        Every replica of one simulation uses the same form, elastic, kernel,
+                        integrator and q3d (one compiled variant serves all replicas of a launch). */
   int32_t integrator;/* corrector (Sec. 3.1): 0 kick-drift-kick, u^{n+1} = u^{n+1/2} + a^{n+1/2} dt/2,
                         r^{n+1} = r^{n+1/2} + u^{n+1} dt/2; 1 midpoint, u^{n+1} = u^n + a^{n+1/2} dt,
                         r^{n+1} = r^n + u^{n+1/2} dt. Both add the APD shift to r and use the same
                         predictor and density update. */
-  int32_t reserved;  /* 0 */
+  int32_t q3d;       /* order tensor: 0 the 2x2 Q of d = 2 (I/2); 1 quasi-2D, a 3x3 Q in the in-plane
+                        flow with the printed I/3 in Eqs. corotation and molecularfielddis, the rate
+                        projected on traceless tensors; Qxx, Qxy, Qyy are stored (Qzz = -Qxx - Qyy,
+                        set with nem_set_qyy; default Qyy = -Qxx). Needs form 0 and elastic 0; the
+                        learned step is not available for it. */
 } nem_params;
 
 /* FP64 global reductions at the current integer time level. */
@@ -117,6 +122,13 @@ int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const
 /* Read the state of replica r into caller host arrays (any may be NULL). */
 int nem_get_state(nem_sim* s, int32_t r, double* x, double* y, double* ux, double* uy, double* qxx,
                   double* qxy, double* rho, double* ax, double* ay);
+
+/* Quasi-2D variant (q3d = 1) only: Qyy of replica r from or to caller host
+ * arrays of n[r] doubles in id order (Qzz = -Qxx - Qyy). nem_set_state sets
+ * Qyy = -Qxx (no out-of-plane part); call nem_set_qyy after it. NEM_E_INVAL
+ * for a simulation with q3d = 0, NEM_E_STATE before nem_set_state. */
+int nem_set_qyy(nem_sim* s, int32_t r, const double* qyy);
+int nem_get_qyy(nem_sim* s, int32_t r, double* qyy);
 
 /* Advance every replica by nsteps time steps (asynchronous). */
 int nem_step(nem_sim* s, int64_t nsteps);

@@ -44,13 +44,13 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
-            "nem_track", "nem_mixing")
+            "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy")
 
 
 class NemParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("L", "dx", "h", "rho0", "eta", "Gamma", "lam", "A", "B", "C", "K",
                                           "zeta", "dt", "gamma_eos", "beta", "c0_factor", "skin")] + \
-               [(k, C.c_int32) for k in ("form", "elastic", "apd", "kernel", "integrator", "reserved")]
+               [(k, C.c_int32) for k in ("form", "elastic", "apd", "kernel", "integrator", "q3d")]
 
 
 class NemDiag(C.Structure):
@@ -108,6 +108,10 @@ def lib(path: Optional[str] = None):
     L.nem_defects.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.nem_vorticity_correlation.restype = C.c_int
     L.nem_vorticity_correlation.argtypes = [vp, C.c_int32, C.c_int32, dp, dp, dp, dp]
+    L.nem_set_qyy.restype = C.c_int
+    L.nem_set_qyy.argtypes = [vp, C.c_int32, dp]
+    L.nem_get_qyy.restype = C.c_int
+    L.nem_get_qyy.argtypes = [vp, C.c_int32, dp]
     L.nem_track.restype = C.c_int
     L.nem_track.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32, dp, dp]
     L.nem_mixing.restype = C.c_int
@@ -161,7 +165,7 @@ def make_params(p) -> NemParams:
     return NemParams(L=p.L, dx=p.dx, h=p.h, rho0=p.rho0, eta=p.eta, Gamma=p.Gamma, lam=p.lam, A=p.A, B=p.B,
                      C=p.C, K=p.K, zeta=p.zeta, dt=p.dt, gamma_eos=p.gamma_eos, beta=p.beta,
                      c0_factor=p.c0_factor, skin=p.skin, form=p.form, elastic=p.elastic, apd=p.apd, kernel=p.kernel,
-                     integrator=p.integrator, reserved=0)
+                     integrator=p.integrator, q3d=getattr(p, "q3d", 0))
 
 
 def _dp(a):
@@ -416,9 +420,27 @@ class Sim:
     def set_state(self, r: int, f: Dict[str, np.ndarray]):
         nem_set_state(self.h, r, f["x"], f["y"], f["ux"], f["uy"], f["qxx"], f["qxy"], f["rho"],
                       f.get("ax"), f.get("ay"))
+        if getattr(self.params[r], "q3d", 0) and "qyy" in f:
+            self.set_qyy(r, f["qyy"])
 
     def get_state(self, r: int = 0) -> Dict[str, np.ndarray]:
-        return nem_get_state(self.h, r, self.n[r])
+        out = nem_get_state(self.h, r, self.n[r])
+        if getattr(self.params[r], "q3d", 0):
+            out["qyy"] = self.get_qyy(r)
+            out["qzz"] = -out["qxx"] - out["qyy"]
+        return out
+
+    def set_qyy(self, r: int, qyy):
+        """Qyy of the quasi-2D variant (after set_state)."""
+        a = np.ascontiguousarray(qyy, dtype=np.float64)
+        if a.size != self.n[r]:
+            raise ValueError("one value per particle")
+        _check(self.h, lib().nem_set_qyy(C.c_void_p(self.h), r, _dp(a)), "nem_set_qyy")
+
+    def get_qyy(self, r: int = 0):
+        a = np.zeros(self.n[r])
+        _check(self.h, lib().nem_get_qyy(C.c_void_p(self.h), r, _dp(a)), "nem_get_qyy")
+        return a
 
     def step(self, nsteps: int):
         nem_step(self.h, nsteps)

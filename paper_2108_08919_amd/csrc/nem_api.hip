@@ -49,6 +49,8 @@ int check_params(const nem_params& p, int64_t n, std::string& why) {
   if (n < 1 || n > (int64_t)1 << 30) return bad("particle count out of range");
   if (p.kernel != 0 && p.kernel != 1) return bad("kernel must be 0 (quintic spline) or 1 (Wendland C2)");
   if (p.integrator != 0 && p.integrator != 1) return bad("integrator must be 0 (kick-drift-kick) or 1 (midpoint)");
+  if (p.q3d != 0 && p.q3d != 1) return bad("q3d must be 0 (2x2 Q) or 1 (quasi-2D 3x3 Q)");
+  if (p.q3d == 1 && (p.form != 0 || p.elastic != 0)) return bad("the quasi-2D Q needs form 0 and elastic 0");
   if (cells_per_side(p) < 3) return bad("box side must hold three cells of side >= kappa h + skin");
   if (p.form != 0 && p.form != 1) return bad("form must be 0 or 1");
   if (p.elastic != 0 && p.elastic != 1) return bad("elastic must be 0 or 1");
@@ -73,6 +75,7 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   R.R2 = (float)(rs * rs);
   R.kern = p.kernel;
   R.integ = p.integrator;
+  R.q3d = p.q3d;
   if (p.kernel == 1) {
     const double a2 = 7.0 / (4.0 * M_PI * p.h * p.h);
     R.a2 = (float)a2; R.W0 = (float)a2; R.dWc = (float)(-5.0 * a2 / (p.h * p.h));
@@ -95,8 +98,8 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
 // Offsets of every buffer for given sizes (shared by nem_arena_bytes and carve()).
 struct Offs {
   size_t reps, work, cell_start, count, cursor, perm;
-  size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id, t_img;
-  size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell, img;
+  size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id, t_img, t_qyy;
+  size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell, img, qyy0, qyy1;
   size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe, vl, vcnt, off_build;
   size_t total;
 };
@@ -120,6 +123,7 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.t_acc = L.put(sizeof(float2) * N);
   o.t_id = L.put(sizeof(int) * N);
   o.t_img = L.put(sizeof(int2) * N);
+  o.t_qyy = L.put(sizeof(float) * N);
   o.off0 = L.put(sizeof(float2) * N);
   o.off1 = L.put(sizeof(float2) * N);
   o.offlo = L.put(sizeof(float2) * N);
@@ -131,6 +135,8 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.id = L.put(sizeof(int) * N);
   o.cell = L.put(sizeof(int) * N);
   o.img = L.put(sizeof(int2) * N);
+  o.qyy0 = L.put(sizeof(float) * N);
+  o.qyy1 = L.put(sizeof(float) * N);
   o.V = L.put(sizeof(float) * N);
   o.bk = L.put(sizeof(float4) * N);
   o.dh = L.put(sizeof(float) * N);
@@ -162,8 +168,9 @@ int sizes_for(const nem_params* p, const int64_t* n, int R, Sizes& s, std::strin
     int rc = check_params(p[r], n[r], why);
     if (rc) return rc;
     // one launch per pass serves every replica: the compiled variant is shared
-    if (p[r].form != p[0].form || p[r].elastic != p[0].elastic || p[r].kernel != p[0].kernel) {
-      why = "replicas of one simulation must share form, elastic and kernel";
+    if (p[r].form != p[0].form || p[r].elastic != p[0].elastic || p[r].kernel != p[0].kernel ||
+        p[r].q3d != p[0].q3d || p[r].integrator != p[0].integrator) {
+      why = "replicas of one simulation must share form, elastic, kernel, q3d and integrator";
       return NEM_E_INVAL;
     }
     const int nc = cells_per_side(p[r]);
@@ -185,9 +192,10 @@ SortArgs sort_args(nem_sim* s, const unsigned* gate) {
   a.reps = s->d_reps; a.R = s->R; a.ncells = s->ncells; a.ntot = s->ntot;
   a.cell_start = s->cell_start; a.count = s->count; a.cursor = s->cursor; a.perm = s->perm;
   a.t_key = s->t_key; a.t_off = s->t_off; a.t_lo = s->t_lo; a.t_u = s->t_u; a.t_q = s->t_q;
-  a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id; a.t_img = s->t_img;
+  a.t_drho = s->t_drho; a.t_acc = s->t_acc; a.t_id = s->t_id; a.t_img = s->t_img; a.t_qyy = s->t_qyy;
   a.off = s->off[s->parity]; a.offlo = s->offlo; a.u = s->u; a.q = s->q[s->parity];
   a.drho = s->drho; a.acc = s->acc; a.id = s->id; a.cell = s->cell; a.img = s->img;
+  a.qyy = s->qyy[s->parity];
   a.flags = s->flags; a.gate = gate; a.off_build = s->off_build;
   return a;
 }
@@ -199,6 +207,7 @@ StepArgs step_args(nem_sim* s) {
   a.cell_start = s->cell_start; a.ncells = s->ncells; a.ntot = s->ntot;
   a.off_cur = s->off[c]; a.off_nxt = s->off[x]; a.offlo = s->offlo; a.u = s->u;
   a.q_cur = s->q[c]; a.q_nxt = s->q[x]; a.acc = s->acc; a.drho = s->drho; a.cell = s->cell;
+  a.qyy_cur = s->qyy[c]; a.qyy_nxt = s->qyy[x];
   a.V = s->V; a.bk = s->bk; a.dh = s->dh; a.apart = s->apart; a.uv = s->uv; a.pi = s->pi;
   a.P = s->P; a.drhat = s->drhat; a.flags = s->flags;
   a.umax_cur = s->umax + (size_t)c * s->R * UMAX_SLOTS; a.umax_nxt = s->umax + (size_t)x * s->R * UMAX_SLOTS;
@@ -289,7 +298,8 @@ struct Timed {
 // Enqueue one step (rebin if requested, step-begin, passes A-D) on stream st
 // for the current parity.
 int enqueue_step(nem_sim* s, hipStream_t st) {
-  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic, s->hp[0].kernel};
+  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic, s->hp[0].kernel, s->hp[0].q3d,
+                    s->hp[0].integrator};
   {
     Timed t(s, 0);
     SortArgs a = sort_args(s, s->flags + 1);
@@ -477,10 +487,12 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   s->t_key = (int*)(b + o.t_key); s->t_off = (float2*)(b + o.t_off); s->t_lo = (float2*)(b + o.t_lo);
   s->t_u = (float2*)(b + o.t_u); s->t_q = (float2*)(b + o.t_q); s->t_drho = (float*)(b + o.t_drho);
   s->t_acc = (float2*)(b + o.t_acc); s->t_id = (int*)(b + o.t_id); s->t_img = (int2*)(b + o.t_img);
+  s->t_qyy = (float*)(b + o.t_qyy);
   s->off[0] = (float2*)(b + o.off0); s->off[1] = (float2*)(b + o.off1); s->offlo = (float2*)(b + o.offlo);
   s->u = (float2*)(b + o.u); s->q[0] = (float2*)(b + o.q0); s->q[1] = (float2*)(b + o.q1);
   s->drho = (float*)(b + o.drho); s->acc = (float2*)(b + o.acc); s->id = (int*)(b + o.id);
   s->cell = (int*)(b + o.cell); s->img = (int2*)(b + o.img);
+  s->qyy[0] = (float*)(b + o.qyy0); s->qyy[1] = (float*)(b + o.qyy1);
   s->V = (float*)(b + o.V); s->bk = (float4*)(b + o.bk); s->dh = (float*)(b + o.dh);
   s->apart = (float2*)(b + o.apart); s->uv = (float*)(b + o.uv); s->pi = (float2*)(b + o.pi);
   s->P = (float*)(b + o.P); s->drhat = (float*)(b + o.drhat);
@@ -530,6 +542,38 @@ int nem_set_state(nem_sim* s, int32_t r, const double* x, const double* y, const
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s->stream));
   s->has_state[r] = 1;
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_set_qyy(nem_sim* s, int32_t r, const double* qyy) {
+  if (!s || r < 0 || r >= s->R || !qyy) return NEM_E_INVAL;
+  if (!s->has_state[r]) { s->err = "set the state before Qyy"; return NEM_E_STATE; }
+  if (!s->hp[r].q3d) { s->err = "Qyy is a state variable of the quasi-2D variant (q3d = 1) only"; return NEM_E_INVAL; }
+  const int n = (int)s->n[r];
+  HIPCHK(hipMemcpyAsync(s->stage, qyy, sizeof(double) * n, hipMemcpyHostToDevice, s->stream));
+  SortArgs a = sort_args(s, nullptr);
+  launch_qyy_io(a, r, n, s->stage, 1, s->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_get_qyy(nem_sim* s, int32_t r, double* qyy) {
+  if (!s || r < 0 || r >= s->R || !qyy) return NEM_E_INVAL;
+  if (!s->has_state[r]) { s->err = "state of this replica was never set"; return NEM_E_STATE; }
+  if (!s->hp[r].q3d) { s->err = "Qyy is a state variable of the quasi-2D variant (q3d = 1) only"; return NEM_E_INVAL; }
+  const int n = (int)s->n[r];
+  SortArgs a = sort_args(s, nullptr);
+  launch_qyy_io(a, r, n, s->stage, 0, s->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(qyy, s->stage, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
   unsigned f[2];
   int rc = read_flags(s, f);
   if (rc) return rc;
@@ -618,7 +662,7 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {
   launch_int_offsets(a, s->t_off, s->stream);
   StepArgs sa = step_args(s);
   sa.off_cur = s->t_off;
-  const PassCfg cfg{s->T, 1, 1, 0, 0, s->hp[0].kernel};
+  const PassCfg cfg{s->T, 1, 1, 0, 0, s->hp[0].kernel, 0, 0};
   if (!launch_pass(1, cfg, sa, s->stream)) return NEM_E_INVAL;
   launch_free_energy(s->T, s->hp[0].kernel, sa, s->fe, s->stream);
   launch_reduce(a, r, (int)s->n[r], s->fe, s->red, s->stream);

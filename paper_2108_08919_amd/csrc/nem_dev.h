@@ -42,6 +42,7 @@ struct RepDev {
   int elastic, apd;
   int kern;        // smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
   int integ;       // corrector: 0 kick-drift-kick, 1 midpoint
+  int q3d;         // 0: 2x2 Q (d = 2); 1: quasi-2D 3x3 Q with I/3 (Qyy stored, Qzz = -Qxx - Qyy)
   float R2v;       // Verlet list radius: fl32((kappa h + delta)^2), delta = 0.1 h
   float disp2;     // rebuild the Verlet list when a particle moved more than 0.45 delta: (0.45 delta)^2
   double csd, Ld;
@@ -62,6 +63,8 @@ struct StepArgs {
   float2* u;              // u^{n+1/2}
   const float2* q_cur;    // (Qxx, Qxy) at Q^n
   float2* q_nxt;          // Q^{n+1}
+  const float* qyy_cur;   // Qyy^n (quasi-2D variant only)
+  float* qyy_nxt;         // Qyy^{n+1}
   float2* acc;            // a^{n+1/2} (kept for read-back and restart)
   float* drho;            // rho^n - rho0, then rho^{n+1} - rho0
   int* cell;              // global cell of each particle (from the last binning)
@@ -88,7 +91,7 @@ struct StepArgs {
 };
 
 // Kernel variant of the pair passes.
-struct PassCfg { int T, LPP, COMP, FORM, EL, KERN; };
+struct PassCfg { int T, LPP, COMP, FORM, EL, KERN, Q3, INTEG; };
 
 // Arguments of the binning, ingest, export and reduction kernels.
 struct SortArgs {
@@ -101,10 +104,11 @@ struct SortArgs {
   int* perm;             // [ntot]
   // unsorted staging copy of the persistent fields
   int* t_key; float2* t_off; float2* t_lo; float2* t_u; float2* t_q; float* t_drho; float2* t_acc; int* t_id;
-  int2* t_img;
+  int2* t_img; float* t_qyy;
   // persistent sorted fields
   float2* off; float2* offlo; float2* u; float2* q; float* drho; float2* acc; int* id; int* cell;
   int2* img;             // periodic image of each particle: unwrapped r = r + img * L
+  float* qyy;            // Qyy (quasi-2D variant), current parity
   unsigned* flags;
   const unsigned* gate;  // run only when *gate != 0 (NULL: always)
   const float2* off_build;  // offsets at the last Verlet build (displacement checks)
@@ -122,6 +126,7 @@ void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base
 void launch_step_begin(unsigned* flags, unsigned* umax_nxt, int R, hipStream_t st);
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st);
 void launch_track(const SortArgs& s, int r, int n, int* inv, const int* ids, int nt, double* out, hipStream_t st);
+void launch_qyy_io(const SortArgs& s, int r, int n, double* buf, int to_device, hipStream_t st);
 void launch_colour_counts(const SortArgs& s, int r, int n, const uint8_t* colour, int ncol, int B,
                           unsigned long long* counts, hipStream_t st);
 void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* red, hipStream_t st);

@@ -37,7 +37,10 @@ __global__ __launch_bounds__(WG) void k_deposit(const StepArgs a, int rep_only, 
     const int g = staged_global<T>(a, L, t);
     s_off[t] = a.off_cur[g];
     const float2 u = a.u[g], ac = a.acc[g], q = a.q_cur[g];
-    s_f[t] = make_float4(u.x - hdt * ac.x, u.y - hdt * ac.y, q.x, q.y);
+    // third field: Qxx in d = 2; (Qxx - Qyy)/2, the in-plane traceless part, in
+    // the quasi-2D variant (the same director angle atan2(Qxy, .)/2)
+    const float qa = R.q3d ? 0.5f * (q.x - a.qyy_cur[g]) : q.x;
+    s_f[t] = make_float4(u.x - hdt * ac.x, u.y - hdt * ac.y, qa, q.y);
   }
   __syncthreads();
   const int tile = a.work[2 * blockIdx.x + 1];

@@ -238,7 +238,7 @@ namespace nem_host {
 void free_snapshot(nem_sim* s) {
   for (auto& S : s->snap) {
     for (void* p : {(void*)S.off, (void*)S.offlo, (void*)S.u, (void*)S.q, (void*)S.acc, (void*)S.drho, (void*)S.id,
-                    (void*)S.cell, (void*)S.img, (void*)S.cell_start, (void*)S.umax})
+                    (void*)S.cell, (void*)S.img, (void*)S.qyy, (void*)S.cell_start, (void*)S.umax})
       if (p) hipFree(p);
     S = nem_sim::Snap();
   }
@@ -257,6 +257,7 @@ int take_snapshot(nem_sim* s, int i) {
     HIPCHK(hipMalloc((void**)&S.id, sizeof(int) * N));
     HIPCHK(hipMalloc((void**)&S.cell, sizeof(int) * N));
     HIPCHK(hipMalloc((void**)&S.img, sizeof(int2) * N));
+    HIPCHK(hipMalloc((void**)&S.qyy, sizeof(float) * N));
     HIPCHK(hipMalloc((void**)&S.cell_start, sizeof(int) * (C + 1)));
     HIPCHK(hipMalloc((void**)&S.umax, sizeof(unsigned) * (s->R * UMAX_SLOTS + 1)));  // + rebin request
     S.alloc = true;
@@ -273,6 +274,7 @@ int take_snapshot(nem_sim* s, int i) {
   add(s->offlo, S.offlo, sizeof(float2) * N);
   add(s->u, S.u, sizeof(float2) * N);
   add(s->q[p], S.q, sizeof(float2) * N);
+  add(s->qyy[p], S.qyy, sizeof(float) * N);
   add(s->acc, S.acc, sizeof(float2) * N);
   add(s->drho, S.drho, sizeof(float) * N);
   add(s->id, S.id, sizeof(int) * N);
@@ -307,6 +309,7 @@ int restore_snapshot(nem_sim* s, int i) {
   add(S.offlo, s->offlo, sizeof(float2) * N);
   add(S.u, s->u, sizeof(float2) * N);
   add(S.q, s->q[p], sizeof(float2) * N);
+  add(S.qyy, s->qyy[p], sizeof(float) * N);
   add(S.acc, s->acc, sizeof(float2) * N);
   add(S.drho, s->drho, sizeof(float) * N);
   add(S.id, s->id, sizeof(int) * N);
@@ -532,6 +535,7 @@ void nem_mlp_destroy(nem_mlp* m) {
 
 int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
   if (!s || mult < 2 || !X || !T) return NEM_E_INVAL;
+  if (s->hp[0].q3d) { s->err = "the learned corrector covers the 2x2 Q only"; return NEM_E_INVAL; }
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) return NEM_E_STATE;
   int rc = take_snapshot(s);
@@ -577,6 +581,7 @@ int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
 int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, double tau, int64_t* n_fallback,
                      double* max_norm) {
   if (!s || !m || n_macro < 0 || mult < 2 || !(tau > 0)) return NEM_E_INVAL;
+  if (s->hp[0].q3d) { s->err = "the learned corrector covers the 2x2 Q only"; return NEM_E_INVAL; }
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) return NEM_E_STATE;
   const size_t N = (size_t)s->ntot;

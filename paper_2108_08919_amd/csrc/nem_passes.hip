@@ -355,8 +355,12 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------------ pass B
-template <int T, int COMP, int FORM, int EL, int KERN>
+// Q3 = 1: quasi-2D variant, a 3x3 order tensor (Qxx, Qxy, Qyy stored,
+// Qzz = -Qxx - Qyy) with the printed I/3 in the co-rotation and the molecular
+// field; corrected momentum form without the lambda stress terms only.
+template <int T, int COMP, int FORM, int EL, int KERN, int Q3>
 __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
+  static_assert(Q3 == 0 || (FORM == 0 && EL == 0), "quasi-2D: corrected form, no lambda terms");
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
@@ -364,6 +368,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
   __shared__ float2 s_q[MP];
   __shared__ float s_V[MP];
   __shared__ float s_rho[FORM == 1 ? MP : 1];
+  __shared__ float s_qc[Q3 == 1 ? MP : 1];   // Qyy of the quasi-2D variant
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -374,6 +379,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     s_off[t] = a.off_cur[g];
     s_u[t] = a.u[g];
     s_q[t] = a.q_cur[g];
+    if constexpr (Q3 == 1) s_qc[t] = a.qyy_cur[g];
     s_V[t] = a.V[g];
     if constexpr (FORM == 1) s_rho[t] = R.rho0 + a.drho[g];
   }
@@ -395,17 +401,21 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     Acc<COMP> Sxx, Sxy, Syy, Gxx, Gxy, Gyx, Gyy, Qax, Qay, Qbx, Qby;
     Acc<COMP> Mxx_a, Mxy_a, Myy_a, Mxx_b, Mxy_b, Myy_b, Vsx, Vsy, Wux, Wuy;
     Acc<COMP> Kc, V1x, V1y, A1x, A1y;
+    Acc<COMP> Qcx, Qcy, Mxx_c, Mxy_c, Myy_c;   // quasi-2D: gradient and Laplacian sums of Qyy
     Sxx.init(); Sxy.init(); Syy.init(); Gxx.init(); Gxy.init(); Gyx.init(); Gyy.init();
     Qax.init(); Qay.init(); Qbx.init(); Qby.init();
     Mxx_a.init(); Mxy_a.init(); Myy_a.init(); Mxx_b.init(); Mxy_b.init(); Myy_b.init();
     Vsx.init(); Vsy.init(); Wux.init(); Wuy.init();
     Kc.init(); V1x.init(); V1y.init(); A1x.init(); A1y.init();
+    Qcx.init(); Qcy.init(); Mxx_c.init(); Mxy_c.init(); Myy_c.init();
     float2 ui = {0.f, 0.f}, qi = {0.f, 0.f};
+    float qci = 0.f;
     float ri = 1.0f;
     if (act) {
       const float2 oi = s_off[p];
       ui = s_u[p];
       qi = s_q[p];
+      if constexpr (Q3 == 1) qci = s_qc[p];
       if constexpr (FORM == 1) ri = s_rho[p];
       const float ri2inv = 1.0f / (ri * ri);
       const int cnt = min(a.ncnt[g], KMAX);
@@ -427,6 +437,12 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         const float la = -dqa * e2, lb = -dqb * e2;   // (Q_i - Q_j)/r^2
         Mxx_a.fma(la, txx); Mxy_a.fma(la, txy); Myy_a.fma(la, tyy);
         Mxx_b.fma(lb, txx); Mxy_b.fma(lb, txy); Myy_b.fma(lb, tyy);
+        if constexpr (Q3 == 1) {
+          const float dqc = s_qc[j] - qci;
+          Qcx.fma(dqc, cx); Qcy.fma(dqc, cy);
+          const float lc = -dqc * e2;
+          Mxx_c.fma(lc, txx); Mxy_c.fma(lc, txy); Myy_c.fma(lc, tyy);
+        }
         const float sv = -(dux * rx + duy * ry) * e2;  // (u_i - u_j).r_ij / r^2
         if constexpr (FORM == 0) {
           Vsx.fma(sv, cx); Vsy.fma(sv, cy);
@@ -449,6 +465,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         Mxx_b.end_cell(); Mxy_b.end_cell(); Myy_b.end_cell();
         Vsx.end_cell(); Vsy.end_cell(); Wux.end_cell(); Wuy.end_cell();
         if constexpr (FORM == 1) { Kc.end_cell(); V1x.end_cell(); V1y.end_cell(); A1x.end_cell(); A1y.end_cell(); }
+        if constexpr (Q3 == 1) { Qcx.end_cell(); Qcy.end_cell(); Mxx_c.end_cell(); Mxy_c.end_cell(); Myy_c.end_cell(); }
       });
     }
     const float sxx = wave_sum(Sxx.value(), lpp), sxy = wave_sum(Sxy.value(), lpp), syy = wave_sum(Syy.value(), lpp);
@@ -462,6 +479,11 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     const float myyb = wave_sum(Myy_b.value(), lpp);
     const float wux = wave_sum(Wux.value(), lpp), wuy = wave_sum(Wuy.value(), lpp);
     float vsx = 0.f, vsy = 0.f, kc = 0.f, v1x = 0.f, v1y = 0.f, a1x = 0.f, a1y = 0.f;
+    float qcx = 0.f, qcy = 0.f, mxxc = 0.f, mxyc = 0.f, myyc = 0.f;
+    if constexpr (Q3 == 1) {
+      qcx = wave_sum(Qcx.value(), lpp); qcy = wave_sum(Qcy.value(), lpp);
+      mxxc = wave_sum(Mxx_c.value(), lpp); mxyc = wave_sum(Mxy_c.value(), lpp); myyc = wave_sum(Myy_c.value(), lpp);
+    }
     if constexpr (FORM == 0) { vsx = wave_sum(Vsx.value(), lpp); vsy = wave_sum(Vsy.value(), lpp); }
     else {
       kc = wave_sum(Kc.value(), lpp); v1x = wave_sum(V1x.value(), lpp); v1y = wave_sum(V1y.value(), lpp);
@@ -493,21 +515,51 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       // Laplacians: 2 sum_j V_j (Q_i - Q_j) (r_ij . g_ij) / r^2
       const float lapa = 2.0f * (Bxx * mxxa + 2.0f * Bxy * mxya + Byy * myya);
       const float lapb = 2.0f * (Bxx * mxxb + 2.0f * Bxy * mxyb + Byy * myyb);
-      // molecular field (2D: the B term vanishes identically)
       const float qa = qi.x, qb = qi.y;
-      const float trq2 = 2.0f * (qa * qa + qb * qb);
-      const float cbulk = R.A + R.C * trq2;
-      const float Ha = -cbulk * qa + R.K * lapa, Hb = -cbulk * qb + R.K * lapb;
-      // co-rotation projected on symmetric traceless tensors (d = 2)
       const float e12 = 0.5f * (G12 + G21), w12 = 0.5f * (G12 - G21);
-      const float QG = qa * (G11 - G22) + 2.0f * qb * e12;
-      const float Sa = R.lam * (qa * divu + 0.5f * (G11 - G22)) + 2.0f * w12 * qb - 2.0f * R.lam * qa * QG;
-      const float Sb = R.lam * (qb * divu + e12) - 2.0f * w12 * qa - 2.0f * R.lam * qb * QG;
-      a.q_nxt[g] = make_float2(qa + (Sa + R.Gamma * Ha) * R.dt, qb + (Sb + R.Gamma * Hb) * R.dt);
+      float Ha, Hb;
+      float dcy = 0.f;   // d Qyy / dy (quasi-2D)
+      if constexpr (Q3 == 0) {
+        // molecular field (2D: the B term vanishes identically)
+        const float trq2 = 2.0f * (qa * qa + qb * qb);
+        const float cbulk = R.A + R.C * trq2;
+        Ha = -cbulk * qa + R.K * lapa; Hb = -cbulk * qb + R.K * lapb;
+        // co-rotation projected on symmetric traceless tensors (d = 2)
+        const float QG = qa * (G11 - G22) + 2.0f * qb * e12;
+        const float Sa = R.lam * (qa * divu + 0.5f * (G11 - G22)) + 2.0f * w12 * qb - 2.0f * R.lam * qa * QG;
+        const float Sb = R.lam * (qb * divu + e12) - 2.0f * w12 * qa - 2.0f * R.lam * qb * QG;
+        a.q_nxt[g] = make_float2(qa + (Sa + R.Gamma * Ha) * R.dt, qb + (Sb + R.Gamma * Hb) * R.dt);
+      } else {
+        // quasi-2D: Q = [[qa, qb, 0], [qb, qc, 0], [0, 0, qz]], qz = -qa - qc,
+        // D = Q + I/3; E and W in-plane. The rate is projected on traceless
+        // tensors (its trace is (2 lambda/3) div u from the weak compressibility).
+        const float qc = qci, qz = -qa - qc;
+        dcy = qcx * Bxy + qcy * Byy;
+        const float lapc = 2.0f * (Bxx * mxxc + 2.0f * Bxy * mxyc + Byy * myyc);
+        const float lapz = -lapa - lapc;
+        const float t2 = qa * qa + 2.0f * qb * qb + qc * qc + qz * qz;
+        const float cb = R.A + R.C * t2, t3 = t2 * (1.0f / 3.0f);
+        Ha = -cb * qa + R.B * (qa * qa + qb * qb - t3) + R.K * lapa;
+        Hb = -cb * qb + R.B * qb * (qa + qc) + R.K * lapb;
+        const float Hc = -cb * qc + R.B * (qb * qb + qc * qc - t3) + R.K * lapc;
+        const float Hz = -cb * qz + R.B * (qz * qz - t3) + R.K * lapz;
+        const float dxx = qa + (1.0f / 3.0f), dyy = qc + (1.0f / 3.0f), dzz = qz + (1.0f / 3.0f), dxy = qb;
+        const float QG = qa * G11 + qb * (G12 + G21) + qc * G22;
+        const float l2 = 2.0f * R.lam * QG;
+        const float Sxx = 2.0f * R.lam * (G11 * dxx + e12 * dxy) + 2.0f * w12 * dxy - l2 * dxx;
+        const float Sxy = R.lam * (e12 * (dxx + dyy) + dxy * divu) + w12 * (dyy - dxx) - l2 * dxy;
+        const float Syy = 2.0f * R.lam * (e12 * dxy + G22 * dyy) - 2.0f * w12 * dxy - l2 * dyy;
+        const float Szz = -l2 * dzz;
+        const float mxx = Sxx + R.Gamma * Ha, mxy = Sxy + R.Gamma * Hb, myy = Syy + R.Gamma * Hc;
+        const float mtr = (mxx + myy + Szz + R.Gamma * Hz) * (1.0f / 3.0f);
+        a.q_nxt[g] = make_float2(qa + (mxx - mtr) * R.dt, qb + mxy * R.dt);
+        a.qyy_nxt[g] = qc + (myy - mtr) * R.dt;
+      }
       float apx, apy;
       if constexpr (FORM == 0) {
         const float vcx = vsx * Bxx + vsy * Bxy, vcy = vsx * Bxy + vsy * Byy;
-        const float divqx = dax + dby, divqy = dbx - day;
+        // div Q: (dQxx/dx + dQxy/dy, dQxy/dx + dQyy/dy), Qyy = -Qxx in d = 2
+        const float divqx = dax + dby, divqy = (Q3 == 0) ? dbx - day : dbx + dcy;
         apx = 8.0f * R.eta * vcx - R.zeta * divqx;
         apy = 8.0f * R.eta * vcy - R.zeta * divqy;
       } else {
@@ -521,7 +573,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
       }
-      if (a.feat) {  // learned-corrector inputs (storage order): Q, grad u, H, density, activity
+      if (Q3 == 0 && a.feat) {  // learned-corrector inputs (storage order): Q, grad u, H, density, activity
         float* f = a.feat + (size_t)g * 12;
         f[0] = qa; f[1] = qb; f[2] = -qa;
         f[3] = G11; f[4] = G12; f[5] = G21; f[6] = G22;
@@ -599,7 +651,8 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------------ pass D
-template <int T, int COMP, int FORM, int EL, int KERN>
+// INTEG: corrector, 0 kick-drift-kick, 1 midpoint (the integrator parameter picks the variant at launch).
+template <int T, int COMP, int FORM, int EL, int KERN, int INTEG>
 __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T, KERN>::MAXP;
@@ -691,7 +744,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       const float2 uh = a.u[g];
       const float hdt = 0.5f * R.dt;
       float u1x, u1y;                                              // u^{n+1}
-      if (R.integ == 0) {                                          // kick-drift-kick
+      if constexpr (INTEG == 0) {                                  // kick-drift-kick
         u1x = uh.x + hdt * ax; u1y = uh.y + hdt * ay;
       } else {                                                     // midpoint: u^n + a dt,
         const float2 ap = a.acc[g];                                // u^n = u^{n+1/2} - a^{n-1/2} dt/2
@@ -708,7 +761,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       const float unx = u1x + hdt * ax, uny = u1y + hdt * ay;      // u^{n+3/2}
       // r^{n+1} - r^{n+1/2}: u^{n+1} dt/2 (kick-drift-kick) or u^{n+1/2} dt/2
       // (midpoint, r^n + u^{n+1/2} dt), then the next predictor's u^{n+3/2} dt/2
-      const float vdx = R.integ == 0 ? u1x : uh.x, vdy = R.integ == 0 ? u1y : uh.y;
+      const float vdx = INTEG == 0 ? u1x : uh.x, vdy = INTEG == 0 ? u1y : uh.y;
       const float dispx = hdt * vdx + drx + hdt * unx;
       const float dispy = hdt * vdy + dry + hdt * uny;
       // compensated position update: (hi, lo) += disp
@@ -769,6 +822,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
   __shared__ float2 s_off[MP];
   __shared__ float2 s_q[MP];
   __shared__ float s_V[MP];
+  __shared__ float s_qc[MP];   // Qyy (quasi-2D variant)
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, blockIdx.x, L, R, rep)) return;
@@ -779,6 +833,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     s_off[t] = a.off_cur[g];
     s_q[t] = a.q_cur[g];
     s_V[t] = a.V[g];
+    if (R.q3d) s_qc[t] = a.qyy_cur[g];
   }
   __syncthreads();
   const int nin = L.cstart[nint];
@@ -788,8 +843,11 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     const float2 oi = s_off[p], qi = s_q[p];
     Acc<1> Sxx, Sxy, Syy, Qax, Qay, Qbx, Qby, Mxxa, Mxya, Myya, Mxxb, Mxyb, Myyb;
+    Acc<1> Qcx, Qcy, Mxxc, Mxyc, Myyc;
     Sxx.init(); Sxy.init(); Syy.init(); Qax.init(); Qay.init(); Qbx.init(); Qby.init();
     Mxxa.init(); Mxya.init(); Myya.init(); Mxxb.init(); Mxyb.init(); Myyb.init();
+    Qcx.init(); Qcy.init(); Mxxc.init(); Mxyc.init(); Myyc.init();
+    const float qci = R.q3d ? s_qc[p] : 0.0f;
     each_listed(a.nl, a.ntot, g, min(a.ncnt[g], KMAX), 1, 0, [&](uint32_t e) {
       int j; float rx, ry, r2;
       listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
@@ -803,10 +861,15 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
       const float la = -dqa * e2, lb = -dqb * e2;
       Mxxa.fma(la, txx); Mxya.fma(la, txy); Myya.fma(la, tyy);
       Mxxb.fma(lb, txx); Mxyb.fma(lb, txy); Myyb.fma(lb, tyy);
+      if (R.q3d) {
+        const float dqc = s_qc[j] - qci, lc = -dqc * e2;
+        Qcx.fma(dqc, cx); Qcy.fma(dqc, cy);
+        Mxxc.fma(lc, txx); Mxyc.fma(lc, txy); Myyc.fma(lc, tyy);
+      }
     }, [&]() {
       Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell(); Qax.end_cell(); Qay.end_cell(); Qbx.end_cell();
       Qby.end_cell(); Mxxa.end_cell(); Mxya.end_cell(); Myya.end_cell(); Mxxb.end_cell(); Mxyb.end_cell();
-      Myyb.end_cell();
+      Myyb.end_cell(); Qcx.end_cell(); Qcy.end_cell(); Mxxc.end_cell(); Mxyc.end_cell(); Myyc.end_cell();
     });
     const float axx = -Sxx.value(), axy = -Sxy.value(), ayy = -Syy.value();
     const float det = axx * ayy - axy * axy;
@@ -819,12 +882,27 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     const double dbx = Qbx.value() * Bxx + Qby.value() * Bxy, dby = Qbx.value() * Bxy + Qby.value() * Byy;
     const double lapa = 2.0 * (Bxx * Mxxa.value() + 2.0f * Bxy * Mxya.value() + Byy * Myya.value());
     const double lapb = 2.0 * (Bxx * Mxxb.value() + 2.0f * Bxy * Mxyb.value() + Byy * Myyb.value());
-    const double qa = qi.x, qb = qi.y, t2 = 2.0 * (qa * qa + qb * qb);
-    const double bulk = 0.5 * (double)R.A * t2 + 0.25 * (double)R.C * t2 * t2;
+    const double qa = qi.x, qb = qi.y;
+    double bulk, qlq, g2;
+    if (!R.q3d) {
+      const double t2 = 2.0 * (qa * qa + qb * qb);
+      bulk = 0.5 * (double)R.A * t2 + 0.25 * (double)R.C * t2 * t2;
+      // Q:lapQ and sum of squared gradients over the four components of Q
+      qlq = 2.0 * (qa * lapa + qb * lapb);
+      g2 = 2.0 * (dax * dax + day * day + dbx * dbx + dby * dby);
+    } else {
+      // quasi-2D: Q = diag-block [[qa, qb], [qb, qc]] + qz e_z e_z, qz = -qa - qc
+      const double qc = qci, qz = -qa - qc;
+      const double dcx = Qcx.value() * Bxx + Qcy.value() * Bxy, dcy = Qcx.value() * Bxy + Qcy.value() * Byy;
+      const double lapc = 2.0 * (Bxx * Mxxc.value() + 2.0f * Bxy * Mxyc.value() + Byy * Myyc.value());
+      const double t2 = qa * qa + 2.0 * qb * qb + qc * qc + qz * qz;
+      const double t3 = qa * qa * qa + 3.0 * qb * qb * (qa + qc) + qc * qc * qc + qz * qz * qz;
+      bulk = 0.5 * (double)R.A * t2 + (double)R.B / 3.0 * t3 + 0.25 * (double)R.C * t2 * t2;
+      qlq = qa * lapa + 2.0 * qb * lapb + qc * lapc + qz * (-lapa - lapc);
+      const double dzx = -dax - dcx, dzy = -day - dcy;
+      g2 = dax * dax + day * day + 2.0 * (dbx * dbx + dby * dby) + dcx * dcx + dcy * dcy + dzx * dzx + dzy * dzy;
+    }
     const double Vi = s_V[p];
-    // Q:lapQ and sum of squared gradients over the four components of Q
-    const double qlq = 2.0 * (qa * lapa + qb * lapb);
-    const double g2 = 2.0 * (dax * dax + day * day + dbx * dbx + dby * dby);
     fe[g] = Vi * (bulk - 0.5 * (double)R.K * qlq);
     fe[(size_t)a.ntot + g] = Vi * (bulk + 0.5 * (double)R.K * g2);
   }
@@ -921,38 +999,48 @@ struct Waves {
   static constexpr int D = ((T == 4 || KERN == 1) && EL == 0) ? 8 : 1;
 };
 
-template <int T, int COMP, int FORM, int EL, int KERN>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL, KERN>::B)))
+template <int T, int COMP, int FORM, int EL, int KERN, int Q3>
+__global__ __launch_bounds__(WG)
+__attribute__((amdgpu_waves_per_eu(Q3 == 0 ? Waves<T, COMP, FORM, EL, KERN>::B : 1)))
 void k_pass_b(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL, KERN>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL, KERN, Q3>(a, w); __syncthreads(); }
 }
 template <int T, int COMP, int KERN>
 __global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP, KERN>(a, w); __syncthreads(); }
 }
-template <int T, int COMP, int FORM, int EL, int KERN>
+template <int T, int COMP, int FORM, int EL, int KERN, int INTEG>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, FORM, EL, KERN>::D)))
 void k_pass_d(const StepArgs a) {
-  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL, KERN>(a, w); __syncthreads(); }
+  for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_d<T, COMP, FORM, EL, KERN, INTEG>(a, w); __syncthreads(); }
 }
 
 // ------------------------------------------------------------- dispatch
 template <int T, int COMP, int FORM, int EL, int KERN>
-static void launch4(int pass, const StepArgs& a, hipStream_t s) {
+static void launch4(int pass, int q3, int integ, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.grid > 0 ? std::min(a.grid, a.nwork) : a.nwork), block(WG);
   switch (pass) {
     case 1: hipLaunchKernelGGL((k_pass_a<T, COMP, KERN>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL, KERN>), grid, block, 0, s, a); break;
+    case 2:
+      if constexpr (FORM == 0 && EL == 0) {
+        if (q3) { hipLaunchKernelGGL((k_pass_b<T, COMP, 0, 0, KERN, 1>), grid, block, 0, s, a); break; }
+      }
+      hipLaunchKernelGGL((k_pass_b<T, COMP, FORM, EL, KERN, 0>), grid, block, 0, s, a);
+      break;
     case 3: hipLaunchKernelGGL((k_pass_c<T, COMP, KERN>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL, KERN>), grid, block, 0, s, a); break;
+    case 4:
+      if (integ) hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL, KERN, 1>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_pass_d<T, COMP, FORM, EL, KERN, 0>), grid, block, 0, s, a);
+      break;
   }
 }
 
 template <int T, int COMP, int KERN>
 static bool launch_phys(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
-  if (c.FORM == 0 && c.EL == 0) { launch4<T, COMP, 0, 0, KERN>(pass, a, s); return true; }
-  if (c.FORM == 1 && c.EL == 0) { launch4<T, COMP, 1, 0, KERN>(pass, a, s); return true; }
-  if (c.FORM == 0 && c.EL == 1) { launch4<T, COMP, 0, 1, KERN>(pass, a, s); return true; }
+  if (c.Q3 && (c.FORM != 0 || c.EL != 0)) return false;
+  if (c.FORM == 0 && c.EL == 0) { launch4<T, COMP, 0, 0, KERN>(pass, c.Q3, c.INTEG, a, s); return true; }
+  if (c.FORM == 1 && c.EL == 0) { launch4<T, COMP, 1, 0, KERN>(pass, c.Q3, c.INTEG, a, s); return true; }
+  if (c.FORM == 0 && c.EL == 1) { launch4<T, COMP, 0, 1, KERN>(pass, c.Q3, c.INTEG, a, s); return true; }
   return false;
 }
 

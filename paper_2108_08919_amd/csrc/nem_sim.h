@@ -25,8 +25,10 @@ struct nem_sim {
   int *cell_start = nullptr, *count = nullptr, *cursor = nullptr, *perm = nullptr;
   int* t_key = nullptr; float2 *t_off = nullptr, *t_lo = nullptr, *t_u = nullptr, *t_q = nullptr;
   float* t_drho = nullptr; float2* t_acc = nullptr; int* t_id = nullptr; int2* t_img = nullptr;
+  float* t_qyy = nullptr;
   float2* off[2] = {nullptr, nullptr}; float2* offlo = nullptr; float2* u = nullptr;
   float2* q[2] = {nullptr, nullptr}; float* drho = nullptr; float2* acc = nullptr;
+  float* qyy[2] = {nullptr, nullptr};  // quasi-2D variant: Qyy (ping-pong like q)
   int* id = nullptr; int* cell = nullptr;
   int2* img = nullptr;
   float* V = nullptr; float4* bk = nullptr; float* dh = nullptr; float2* apart = nullptr;
@@ -65,6 +67,7 @@ struct nem_sim {
     float* drho = nullptr;
     int *id = nullptr, *cell = nullptr, *cell_start = nullptr;
     int2* img = nullptr;
+    float* qyy = nullptr;
     unsigned* umax = nullptr;  // R * UMAX_SLOTS max-speed slots, then the rebin request
     int parity = 0;
     std::vector<float> dt;

@@ -63,6 +63,7 @@ __global__ void k_ingest(SortArgs s, int r, const double* __restrict__ in, int n
     const float2 uf = make_float2((float)uhx, (float)uhy);
     s.t_u[k] = uf;
     s.t_q[k] = make_float2((float)qxx[i], (float)qxy[i]);
+    s.t_qyy[k] = -(float)qxx[i];   // quasi-2D variant: Qzz = 0 until nem_set_qyy
     s.t_drho[k] = (float)(rho[i] - (double)R.rho0);
     s.t_acc[k] = make_float2((float)ax[i], (float)ay[i]);
     s.t_id[k] = i;
@@ -115,6 +116,7 @@ __global__ void k_rebin_key(SortArgs s) {
     s.t_lo[k] = nl;
     s.t_u[k] = s.u[k];
     s.t_q[k] = s.q[k];
+    s.t_qyy[k] = s.qyy[k];
     s.t_drho[k] = s.drho[k];
     s.t_acc[k] = s.acc[k];
     s.t_id[k] = s.id[k];
@@ -197,6 +199,7 @@ __global__ void k_gather(SortArgs s, int k0, int n, int c0, int nc) {
     s.offlo[k] = s.t_lo[src];
     s.u[k] = s.t_u[src];
     s.q[k] = s.t_q[src];
+    s.qyy[k] = s.t_qyy[src];
     s.drho[k] = s.t_drho[src];
     s.acc[k] = s.t_acc[src];
     s.id[k] = s.t_id[src];
@@ -277,6 +280,19 @@ __global__ void k_export(SortArgs s, int r, double* out, int n) {
   }
 }
 
+// Qyy of replica r (quasi-2D variant) to or from an FP64 array in id order:
+// to_device != 0 copies buf[id] into the sorted array, else the reverse.
+__global__ void k_qyy_io(SortArgs s, int r, int n, double* buf, int to_device) {
+  const RepDev R = s.reps[r];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = R.part_base + i;
+    const int id = s.id[k];
+    if (id < 0 || id >= n) { atomicOr(s.flags, ERR_RANGE); continue; }
+    if (to_device) s.qyy[k] = (float)buf[id];
+    else buf[id] = (double)s.qyy[k];
+  }
+}
+
 // Pathlines: inv[id] = sorted slot of every particle of replica r.
 __global__ void k_track_inv(SortArgs s, int r, int n, int* inv) {
   const RepDev R = s.reps[r];
@@ -348,7 +364,12 @@ __global__ __launch_bounds__(256) void k_reduce1(SortArgs s, int r, int n, const
     const double u2 = ux * ux + uy * uy;
     a0 += ux; a1 += uy; a2 += 0.5 * u2;
     m0 = fmax(m0, sqrt(u2));
-    m1 = fmax(m1, sqrt(2.0 * ((double)q.x * q.x + (double)q.y * q.y)));
+    if (R.q3d) {  // 3x3 Frobenius norm, Qzz = -Qxx - Qyy
+      const double qa = q.x, qb = q.y, qc = s.qyy[k], qz = -qa - qc;
+      m1 = fmax(m1, sqrt(qa * qa + 2.0 * qb * qb + qc * qc + qz * qz));
+    } else {
+      m1 = fmax(m1, sqrt(2.0 * ((double)q.x * q.x + (double)q.y * q.y)));
+    }
     if (fe) { f0 += fe[k]; f1 += fe[(size_t)s.ntot + k]; }
   }
   const int t = threadIdx.x;
@@ -416,6 +437,10 @@ void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* re
 }
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_export, dim3(grid_for(n)), dim3(256), 0, st, s, r, out, n);
+}
+
+void launch_qyy_io(const SortArgs& s, int r, int n, double* buf, int to_device, hipStream_t st) {
+  hipLaunchKernelGGL(k_qyy_io, dim3(grid_for(n)), dim3(256), 0, st, s, r, n, buf, to_device);
 }
 
 void launch_track(const SortArgs& s, int r, int n, int* inv, const int* ids, int nt, double* out, hipStream_t st) {

@@ -89,7 +89,7 @@ def order_tensor3(theta: np.ndarray, q0: float = 1.0):
     an in-plane director at angle theta (the d = 3 form of the paper's Q)."""
     c, s = np.cos(theta), np.sin(theta)
     return (1.5 * q0 * (c * c - 1.0 / 3.0), 1.5 * q0 * c * s, 1.5 * q0 * (s * s - 1.0 / 3.0),
-            np.full_like(theta, -0.5 * q0))
+            -0.5 * q0 * np.ones_like(theta))
 
 
 def initial_state(n_side: int, dx: float, rho0: float, seed: int, kind: str, q0: float = 1.0) -> Dict[str, np.ndarray]:
