@@ -70,8 +70,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick tile and lanes per particle by timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-check", action="store_true", help="also time the hipGraph replay path")
-    ap.add_argument("--workload", choices=("box", "ensemble"), default="box",
-                    help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch")
+    ap.add_argument("--workload", choices=("box", "ensemble", "diagnostics"), default="box",
+                    help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch; "
+                         "diagnostics: time each grid and Lagrangian diagnostic on the box")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device to device once "
                          "(a kernel of known traffic for scaling hardware byte counters)")
@@ -89,6 +90,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "ensemble":
         return ensemble(args)
+    if args.workload == "diagnostics":
+        return diagnostics(args)
     cfg = wl.config("C4")
     p = cfg["params"]
     if args.side != 2048:
@@ -214,6 +217,54 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+def diagnostics(args):
+    """Wall time per call of each diagnostic on the 2048 x 2048 box after a few
+    steps (the calls synchronise and return host arrays, so wall time is the
+    cost a caller sees): FP64 reductions, Shepard deposit, spectrum, defects and
+    vorticity correlation on the M x M grid (M = 2048), pathlines of 4096 tagged
+    particles and the quadrant mixing histogram (512 x 512 bins)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_2108_08919_amd as P
+    cfg = wl.config("C4")
+    p = cfg["params"]
+    n = cfg["n_side"] ** 2
+    s0 = wl.state_for(cfg, 0)
+    ux, uy = wl.smooth_velocity(s0["x"], s0["y"], p.L, 1e-3, 7)
+    s0["ux"], s0["uy"] = ux, uy
+    sim = P.Sim([p], [n])
+    sim.set_state(0, s0)
+    sim.step(10)
+    sim.check()
+    M = cfg["n_side"]
+    ids = np.arange(0, n, n // 4096, dtype=np.int32)
+    colour = ((s0["x"] >= p.L / 2).astype(np.uint8) + 2 * (s0["y"] >= p.L / 2).astype(np.uint8)).astype(np.uint8)
+    calls = {
+        "reductions": lambda: sim.diagnostics(0),
+        "deposit": lambda: sim.deposit(0, M),
+        "spectrum": lambda: sim.spectrum(0, M),
+        "defects": lambda: sim.defects(0, M),
+        "vorticity_correlation": lambda: sim.vorticity_correlation(0, M),
+        "track_4096": lambda: sim.track(ids),
+        "mixing_512": lambda: sim.mixing(colour, 4, 512),
+    }
+    out = {}
+    for name, f in calls.items():
+        f()                                   # first call allocates the grid buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            f()
+        t1 = time.perf_counter()
+        out[name] = 1e3 * (t1 - t0) / 5
+        print(f"[diagnostics] {name}: {out[name]:.3f} ms", file=sys.stderr, flush=True)
+    sim.close()
+    print(json.dumps({"metric": "diagnostic wall time per call", "unit": "ms", "higher_is_better": False,
+                      "config": {"workload": f"{M}x{M} lattice box, {n} particles, grid {M}x{M}"},
+                      "ms": out}), flush=True)
 
 
 def ensemble(args):
