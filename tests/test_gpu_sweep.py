@@ -44,3 +44,15 @@ def test_defect_density_falls_with_elastic_constant():
     d = [rows[k]["defect_density"] for k in (0.01, 0.04, 0.08)]
     print(d, flush=True)
     assert d[0] > 1.05 * d[1] and d[1] > 1.05 * d[2] > 0
+
+
+def test_vortex_size_grows_with_elastic_constant():
+    """Sec. 5: larger K gives larger vortices (the active length sqrt(K/zeta)).
+    Same initial state for every K, so only K differs."""
+    import workloads as wl
+    reps = [dict(name=f"K{k}", n_side=128, params=wl.Params(L=128.0, zeta=0.02, K=k), kind="isotropic", seed=1000)
+            for k in (0.01, 0.04, 0.16)]
+    rec = sweep.run(reps, 5000, 500, 2500, graph=10, autotune=False)
+    ls = [r["l"] for r in rec[:-1]]
+    print("l_omega", ls, flush=True)
+    assert ls[0] < ls[1] < ls[2]
