@@ -39,16 +39,18 @@ extern "C" {
 #define NEM_E_NOMEM (-2)     /* arena too small or allocation failed */
 #define NEM_E_HIP (-3)       /* HIP runtime error */
 #define NEM_E_NUMERIC (-4)   /* a non-finite value appeared in the state */
-#define NEM_E_OVERFLOW (-5)  /* a cell tile exceeds the LDS staging capacity (24 particles per cell on
-                                average), a cell holds more than 48 particles, or a particle has more
-                                than 64 neighbours */
+#define NEM_E_OVERFLOW (-5)  /* a cell tile exceeds the LDS staging capacity (on average 24 particles
+                                per cell of the quintic spline, 10 per cell of Wendland C2), a cell
+                                holds more than 48 particles, or a particle has more than 64
+                                neighbours */
 #define NEM_E_SINGULAR (-6)  /* correction tensor not invertible; B = I was used */
 #define NEM_E_STATE (-7)     /* call order (e.g. step before set_state) */
 #define NEM_E_RANGE (-8)     /* an index fell outside its buffer; the access was skipped */
 
 /* Parameters of one periodic box (one replica). Symbols of the paper:
  * Table 2 (Gamma, lambda, A, B, C, K, zeta, rho), Eq. sphMomentum (nu = eta/rho0),
- * Eq. quintic (h; support 3h), Eq. sphEos (gamma_eos, c0 = c0_factor max|u|),
+ * Eq. quintic (h; support kappa h, kappa = 3, or 2 for the Wendland C2
+ * variant), Eq. sphEos (gamma_eos, c0 = c0_factor max|u|),
  * Eq. densityCorrection (beta). */
 typedef struct nem_params {
   double L;          /* box side */
@@ -140,10 +142,11 @@ int nem_sync(nem_sim* s);
  * (r^{n+1/2}), in CSR by particle id with ascending columns. The GPU keeps no
  * list: this enumerates pairs with the kernels' own predicate. Positions are
  * FP32 offsets o from the corner of the particle's cell (cells of side
- * cs = fl32(L/nc), nc = floor(L/(3h + skin))); for j in the cell displaced by
+ * cs = fl32(L/nc), nc = floor(L/(kappa h + skin))); for j in the cell displaced by
  * d in {-1,0,1}^2 from i's cell, r = fl(fl(o_i - o_j) + fl32(-d cs)) per
  * component, r2 = fl(fl(rx*rx) + fl(ry*ry)) without fused multiply-add, and j
- * is a neighbour when 0 < r2 < fl32((3h)^2) (Eq. quintic: support 3h).
+ * is a neighbour when 0 < r2 < fl32((kappa h)^2) (Eq. quintic: support 3h; 2h
+ * for the Wendland C2 variant).
  * row_ptr has n[r]+1 entries; col has cap entries; *nnz receives the count.
  * Returns NEM_E_NOMEM (with *nnz set) when cap is too small. */
 int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
@@ -158,11 +161,12 @@ int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out);
 /* Grid diagnostics of replica r at the integer time level (paper Sec. 5).
  * All three first Shepard-interpolate u and Q onto an M x M grid (M a power of
  * two in [8, 2048]; nodes at ((i+1/2) L/M, (j+1/2) L/M)): f_g = sum_j f_j W_gj /
- * sum_j W_gj over particles within 3h. These calls allocate grid buffers on the
+ * sum_j W_gj over particles within the kernel support. These calls allocate grid buffers on the
  * device on first use (freed by nem_destroy) and synchronise the stream.
  *
  * nem_deposit: copies the grid to out[4*M*M] = (ux, uy, Qxx, Qxy), each row major
- *   (out[f*M*M + j*M + i]).
+ *   (out[f*M*M + j*M + i]); with q3d = 1 the third field is (Qxx - Qyy)/2, the
+ *   in-plane traceless part, so the director angle reads the same way.
  * nem_spectrum: kinetic-energy spectrum E(n) = 1/2 sum_{shell n} |u^(k)|^2 / M^4
  *   with shell n = floor(|k| L/2pi + 1/2) (so sum_n E(n) = <|u|^2>/2 over the grid),
  *   from a double-precision 2D FFT; E has nbins entries (shells beyond
@@ -216,7 +220,8 @@ int nem_mixing(nem_sim* s, int32_t r, const uint8_t* colour, int32_t ncol, int32
 /* Tuning and instrumentation options (key, value):
  *   NEM_OPT_TILE       cells per tile side (4 or 8)
  *   NEM_OPT_LPP        lanes per particle in the pair loops (1, 2 or 4)
- *   NEM_OPT_COMP       pair-sum compensation: 0 none, 1 per stencil cell, 2 per pair
+ *   NEM_OPT_COMP       pair-sum compensation: 0 none, 1 Kahan over chunks of 16 pairs
+ *                      (default), 2 Kahan on every pair term
  *   NEM_OPT_TIMING     1: record HIP events around every pass launch
  *   NEM_OPT_GRAPH      k > 0: capture k consecutive steps per buffer parity into
  *                      a hipGraph and replay it (steps left over run eagerly;
