@@ -58,3 +58,39 @@ def test_regular_state_after_overflow_in_another_simulation():
     sim.step(3)
     sim.check()
     sim.close()
+
+
+def test_isolated_particles_report_singular_and_match_oracle():
+    """Degenerate case of Eq. sphCorrectionMatrix: particles with no neighbour
+    within 3h have alpha = 0. Both sides fall back to B = I; the GPU raises the
+    sticky NEM_E_SINGULAR, and the fields (u carried unchanged, Q relaxing by
+    its bulk term only) still match the oracle."""
+    import ctypes as C
+    import oracle
+    import paper_2108_08919_amd as P
+    from gpu_common import field_errors, run_oracle
+    L = 32
+    g = (np.arange(4) * 8.0 + 4.0)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    x, y = X.ravel().copy(), Y.ravel().copy()          # 16 particles 8 apart: no pair within 3h
+    n = x.size
+    rng = np.random.default_rng(3)
+    th = rng.uniform(0, np.pi, n)
+    s0 = dict(x=x, y=y, ux=1e-3 * rng.normal(size=n), uy=1e-3 * rng.normal(size=n), qxx=np.cos(2 * th),
+              qxy=np.sin(2 * th), rho=np.ones(n), ax=np.zeros(n), ay=np.zeros(n))
+    p = wl.Params(L=float(L), zeta=0.02)
+    sim = P.Sim([p], [n])
+    sim.set_state(0, s0)
+    sim.step(3)
+    assert sim.sync() == P.NEM_E_SINGULAR
+    out = {k: np.zeros(n) for k in ("x", "y", "ux", "uy", "qxx", "qxy", "rho", "ax", "ay")}
+    rc = P.lib().nem_get_state(C.c_void_p(sim.h), 0, *[out[k].ctypes.data_as(C.POINTER(C.c_double))
+                                                     for k in ("x", "y", "ux", "uy", "qxx", "qxy", "rho", "ax", "ay")])
+    assert rc == P.NEM_E_SINGULAR                         # sticky, the state is still returned
+    o, _ = run_oracle(p, s0, 3)
+    e = field_errors(out, o, s0, L)
+    print({k: f"{v:.3e}" for k, v in e.items()}, flush=True)
+    for k in ("u", "Q", "rho", "pos"):
+        assert e[k] <= 1e-6, (k, e[k])
+    assert np.allclose(out["ux"], s0["ux"], rtol=0, atol=1e-9)   # no force without neighbours
+    sim.close()
