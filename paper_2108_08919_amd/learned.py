@@ -16,7 +16,9 @@ Workloads:
 * evaluation: the 1024 x 1024 box at zeta = K = 0.02 over t in [0, 2] from four
   seeded isotropic starts: plain steps of dt = 1e-3 (reference), plain steps of
   4 dt, and learned macro steps of 4 dt; the errors are those of the ensemble-
-  and time-averaged kinetic energy and defect density over t in [1, 2].
+  and time-averaged kinetic energy and defect density over t in [1, 2], and
+  the relative L2 errors of the final fields against the plain-dt run from the
+  same start (Q relative to its change over the run, u relative to its size).
 
 The fallback threshold tau is the 99.9th percentile of the training
 corrections' norm in the network's normalised output units; a macro step whose
@@ -149,6 +151,9 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
     n = side * side
     res = {"plain": [], "plain_coarse": [], "learned": []}
     times = {"plain": 0.0, "plain_coarse": 0.0, "learned": 0.0}
+    # field errors at the end of the run against the plain-dt fields of the same
+    # start: Q relative to its change over the run, u relative to its size
+    ferr = {"plain_coarse": {"q": [], "u": []}, "learned": {"q": [], "u": []}}
     fallbacks = 0
     k_first = max(1, int(round(t_avg[0] / (mult * dt))))        # macro steps to the window
     k_every = max(1, int(round(every / (mult * dt))))           # macro steps between observations
@@ -156,6 +161,7 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
     spans = [k_first] + [k_every] * (n_obs - 1)
     for s in seeds:
         st = wl.initial_state(side, 1.0, 1.0, seed=3000 + s, kind="isotropic")
+        ref = None
         for mode in ("plain", "plain_coarse", "learned"):
             q = p if mode != "plain_coarse" else p.replace(dt=mult * dt)
             sim = _sim([q], [n])
@@ -177,8 +183,16 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
                 times[mode] += time.perf_counter() - c0
                 obs.append(_observe(sim, side))
             sim.check()
+            f = sim.get_state(0)
             sim.close()
             res[mode].append(obs)
+            q = np.concatenate([f["qxx"], f["qxy"]])
+            u = np.concatenate([f["ux"], f["uy"]])
+            if mode == "plain":
+                ref = (q, u, q - np.concatenate([st["qxx"], st["qxy"]]))
+            else:
+                ferr[mode]["q"].append(float(np.linalg.norm(q - ref[0]) / np.linalg.norm(ref[2])))
+                ferr[mode]["u"].append(float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1])))
             _log(f"evaluated seed {s} {mode}: {times[mode]:.2f} s cumulative")
     out = {"window": [k_first * mult * dt, (k_first + k_every * (n_obs - 1)) * mult * dt], "observations": n_obs}
     ref = np.array(res["plain"])           # seeds x times x (ke, defects)
@@ -188,6 +202,9 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
         out[mode] = {"ke": float(ke), "defect_density": float(de), "seconds": times[mode]}
         out[mode]["eps_ke"] = float(abs(ke - ref[..., 0].mean()) / ref[..., 0].mean())
         out[mode]["eps_defects"] = float(abs(de - ref[..., 1].mean()) / ref[..., 1].mean())
+        if mode in ferr:
+            out[mode]["q_field_err"] = float(np.mean(ferr[mode]["q"]))
+            out[mode]["u_field_err"] = float(np.mean(ferr[mode]["u"]))
     out["speedup_learned_vs_plain"] = times["plain"] / times["learned"] if times["learned"] > 0 else None
     out["speedup_coarse_vs_plain"] = times["plain"] / times["plain_coarse"] if times["plain_coarse"] > 0 else None
     out["fallbacks"] = fallbacks
