@@ -89,7 +89,9 @@ RepDev make_rep(const nem_params& p, int nc, int cell_base, int part_base, int n
   R.dt = (float)p.dt; R.gamma_eos = (float)p.gamma_eos; R.beta = (float)p.beta;
   R.c0_factor = (float)p.c0_factor; R.mass = (float)(p.rho0 * p.dx * p.dx); R.inv_rho0 = (float)(1.0 / p.rho0);
   R.elastic = p.elastic; R.apd = p.apd;
-  const double delta = 0.1 * p.h;  // Verlet skin
+  // Verlet skin: 3h + delta stays below 4 dx for h = 1.3 dx, so the list leaves
+  // out the lattice's ring at 4 dx that a wider skin would carry every step
+  const double delta = 0.075 * p.h;
   R.R2v = (float)((rs + delta) * (rs + delta));
   R.disp2 = (float)((0.45 * delta) * (0.45 * delta));
   return R;

@@ -43,7 +43,7 @@ struct RepDev {
   int kern;        // smoothing kernel: 0 quintic spline (support 3h), 1 Wendland C2 (support 2h)
   int integ;       // corrector: 0 kick-drift-kick, 1 midpoint
   int q3d;         // 0: 2x2 Q (d = 2); 1: quasi-2D 3x3 Q with I/3 (Qyy stored, Qzz = -Qxx - Qyy)
-  float R2v;       // Verlet list radius: fl32((kappa h + delta)^2), delta = 0.1 h
+  float R2v;       // Verlet list radius: fl32((kappa h + delta)^2), delta = 0.075 h
   float disp2;     // rebuild the Verlet list when a particle moved more than 0.45 delta: (0.45 delta)^2
   double csd, Ld;
 };

@@ -183,7 +183,7 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 
 // ------------------------------------------------------------- pass A, Verlet
 // Between builds of the Verlet list (every pair of the 3 x 3 stencil closer
-// than 3h + delta, delta = 0.1 h), pass A walks that list instead of the ~144
+// than 3h + delta, delta = 0.075 h), pass A walks that list instead of the ~144
 // candidates: each listed pair is put through the exact predicate again and the
 // accepted ones make the step's neighbour list, sums and counts, exactly as
 // the candidate search would. The list stays a superset while no particle has
