@@ -60,7 +60,7 @@ typedef struct nem_params {
   double eta;        /* dynamic viscosity */
   double Gamma;      /* rotational diffusivity */
   double lam;        /* flow-alignment (tumbling) parameter lambda */
-  double A, B, C;    /* Landau coefficients (B drops out in 2D) */
+  double A, B, C;    /* Landau coefficients (B drops out with the 2x2 Q of d = 2) */
   double K;          /* elastic constant */
   double zeta;       /* activity */
   double dt;         /* time step */
