@@ -99,7 +99,8 @@ typedef struct nem_diag {
 
 typedef struct nem_sim nem_sim;
 
-/* Library version (major*10000 + minor*100 + patch). */
+/* Library version (major*10000 + minor*100 + patch): 200 is version 0.2.0, the
+ * first with the kernel, integrator and q3d fields of nem_params. */
 int nem_version(void);
 
 /* Device bytes needed for R replicas with n[r] particles each. */

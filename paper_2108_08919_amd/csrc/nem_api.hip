@@ -424,7 +424,7 @@ int upload_reps(nem_sim* s) {
 
 extern "C" {
 
-int nem_version(void) { return 100; }
+int nem_version(void) { return 200; }
 
 const char* nem_strerror(int code) {
   switch (code) {
