@@ -115,59 +115,57 @@ __device__ __forceinline__ bool pair_accept(float oix, float oiy, float ojx, flo
 // Smoothing kernels of support kappa h (2D), selected at compile time:
 //   KERN 0: quintic spline, kappa = 3 (Eq. quintic; the paper's kernel),
 //   KERN 1: Wendland C2, kappa = 2, W = a2 (1 - q/2)^4 (1 + 2q), a2 = 7/(4 pi h^2).
-// Each returns W and F = (dW/dr)/r, so that grad_i W_ij = F r_ij.
+// F = (dW/dr)/r, so that grad_i W_ij = F r_ij.
+// kernel_raw returns W and F without the replica's constant factors,
+// Wr = W / a2 and Fr = F / dWc: the pair loops apply a2 once per particle after
+// the sum and fold dWc into a staged per-particle factor (the volume), which
+// takes two multiplies out of every pair.
+//   quintic:     Wr = t3^5 - 6 t2^5 + 15 t1^5, Fr = (t3^4 - 6 t2^4 + 15 t1^4) / r,
+//                t_m = (m - q)_+, q = r/h (dW/dr = dWc (...), dWc = -5 a2 / h);
+//   Wendland C2: Wr = (1 - q/2)^4 (1 + 2q), Fr = (1 - q/2)^3 (dWc = -5 a2 / h^2).
 // r2 is positive and far above the FP32 denormal range for every accepted pair
 // (particles never come within 1e-19 of each other), so the hardware
 // reciprocal square root is used without the denormal rescaling of rsqrtf.
+// Every listed pair has r < 3h up to rounding, so t3 needs no clamp.
 struct KW { float rinv, r, W, F; };
 template <int KERN>
-__device__ __forceinline__ KW kernel_wf(const RepDev& R, float r2) {
+__device__ __forceinline__ KW kernel_raw(const RepDev& R, float r2) {
   KW k;
   k.rinv = __builtin_amdgcn_rsqf(r2);
   k.r = r2 * k.rinv;
-  const float b = k.r * R.hinv;
+  const float b = k.r * R.hinv;   // q
   if constexpr (KERN == 0) {
     const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
     const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
     const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
-    const float P4 = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34));
-    const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
-    k.W = R.a2 * P5;
-    k.F = R.dWc * P4 * k.rinv;   // dW/dr = dWc P4
+    k.W = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
+    k.F = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34)) * k.rinv;
   } else {
-    // dW/dr = -5 a2 q (1 - q/2)^3 / h, so F = dWc (1 - q/2)^3 with dWc = -5 a2 / h^2
     const float t = fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f);
-    const float t2 = t * t, t3 = t2 * t;
-    k.W = R.a2 * (t2 * t2) * fmaf(2.0f, b, 1.0f);
-    k.F = R.dWc * t3;
+    const float t2 = t * t;
+    k.W = (t2 * t2) * fmaf(2.0f, b, 1.0f);
+    k.F = t2 * t;
   }
   return k;
 }
 
-// W only, also returning 1/r and r.
+// W(0) / a2: the self term of the kernel sums in units of a2.
 template <int KERN>
-__device__ __forceinline__ float kernel_wr(const RepDev& R, float r2, float& rinv, float& r) {
-  rinv = __builtin_amdgcn_rsqf(r2);
-  r = r2 * rinv;
-  const float b = r * R.hinv;
-  if constexpr (KERN == 0) {
-    const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
-    const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
-    const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
-    const float P5 = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
-    return R.a2 * P5;
-  } else {
-    const float t = fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f);
-    const float t2 = t * t;
-    return R.a2 * (t2 * t2) * fmaf(2.0f, b, 1.0f);
-  }
+constexpr float kernel_w0_raw() { return KERN == 0 ? 66.0f : 1.0f; }
+
+// W and F with their constant factors (passes off the step's hot path).
+template <int KERN>
+__device__ __forceinline__ KW kernel_wf(const RepDev& R, float r2) {
+  KW k = kernel_raw<KERN>(R, r2);
+  k.W *= R.a2;
+  k.F *= R.dWc;
+  return k;
 }
 
-// Same without the derivative (passes that need W only).
+// W only.
 template <int KERN>
 __device__ __forceinline__ float kernel_w(const RepDev& R, float r2) {
-  float rinv, r;
-  return kernel_wr<KERN>(R, r2, rinv, r);
+  return R.a2 * kernel_raw<KERN>(R, r2).W;
 }
 
 // A pair-sum accumulator. COMP 0: plain FP32 sum. COMP 1: Kahan summation over
@@ -205,7 +203,8 @@ struct Acc {
       s = t;
     }
   }
-  // This lane's compensated value.
+  // This lane's compensated value. For COMP 1, s + p is also what closing an
+  // open chunk would give (its rounded sum), so none is closed before this.
   __device__ __forceinline__ float value() const {
     if constexpr (COMP == 0) return s;
     else if constexpr (COMP == 1) return s + p;

@@ -56,21 +56,45 @@ __device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int
   pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, 3.4e38f, rx, ry, r2);
 }
 
+// The 32-bit words of one particle's list (two 16-bit entries each, rows
+// `stride` words apart), each loaded two words before it is used so that the
+// load's latency overlaps the pair work of the words before it.
+struct ListStream {
+  const uint32_t* p;
+  size_t stride;
+  int nw, m;
+  uint32_t w0, w1;
+  __device__ __forceinline__ ListStream(const uint32_t* p_, size_t stride_, int nwords)
+      : p(p_), stride(stride_), nw(nwords), m(2) {
+    w0 = nw > 0 ? p[0] : 0u;
+    w1 = nw > 1 ? p[stride] : 0u;
+  }
+  __device__ __forceinline__ uint32_t next() {
+    const uint32_t w = w0;
+    w0 = w1;
+    w1 = m < nw ? p[(size_t)m * stride] : 0u;
+    ++m;
+    return w;
+  }
+};
+
 // Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
-// sub, sub+lpp, ...; flush() closes a compensation chunk every 16 pairs.
+// sub, sub+lpp, ...; flush() closes a compensation chunk every 16 pairs (the
+// last, open chunk is summed by the accumulators' value()).
 template <typename Body, typename Flush>
 __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int ntot, int g, int cnt, int lpp,
                                             int sub, Body&& body, Flush&& flush) {
   const uint32_t* p = nl + g;
   if (lpp == 1) {
+    ListStream ls(p, (size_t)ntot, (cnt + 1) >> 1);
     int k = 0;
     for (; k + 1 < cnt; k += 2) {
-      const uint32_t w = p[(size_t)(k >> 1) * ntot];
+      const uint32_t w = ls.next();
       body(w & 0xFFFFu);
       body(w >> 16);
       if ((k & 15) == 14) flush();
     }
-    if (k < cnt) body(p[(size_t)(k >> 1) * ntot] & 0xFFFFu);
+    if (k < cnt) body(ls.next() & 0xFFFFu);
   } else {
     int it = 0;
     for (int k = sub; k < cnt; k += lpp, ++it) {
@@ -79,7 +103,6 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
       if ((it & 15) == 15) flush();
     }
   }
-  flush();
 }
 
 // ------------------------------------------------------------------ pass A
@@ -164,18 +187,17 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
       const float2 oj = s_off[j];
       float rx, ry, r2;
       pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2);
-      float rinv, r;
-      sw.add(kernel_wr<KERN>(R, r2, rinv, r));
-      const float r3 = rinv * rinv * rinv;
-      sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
+      const KW kw = kernel_raw<KERN>(R, r2);
+      sw.add(kw.W);
+      const float r3 = kw.rinv * kw.rinv * kw.rinv;
+      sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(kw.r);
       const uint32_t e = (uint32_t)j | (hi & 0xF000u);
       if (k & 1) dst[(size_t)(k >> 1) * a.ntot] = word | (e << 16);
       else word = e;
       if ((k & 15) == 15) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
     }
     if (kept & 1) dst[(size_t)(kept >> 1) * a.ntot] = word;
-    sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
-    a.V[g] = 1.0f / (R.W0 + sw.value());
+    a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
     a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)kept);
     a.ncnt[g] = kept;
   }
@@ -207,10 +229,10 @@ struct ExactSink {
     kept = 0; word = 0u; dst = a.nl + g; ntot = a.ntot;
   }
   __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
-    float rinv, r;
-    sw.add(kernel_wr<KERN>(R, r2, rinv, r));
-    const float r3 = rinv * rinv * rinv;
-    sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(r);
+    const KW kw = kernel_raw<KERN>(R, r2);
+    sw.add(kw.W);
+    const float r3 = kw.rinv * kw.rinv * kw.rinv;
+    sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(kw.r);
     if (kept < KMAX) {
       if (kept & 1) dst[(size_t)(kept >> 1) * ntot] = word | (e << 16);
       else word = e;
@@ -221,9 +243,8 @@ struct ExactSink {
   __device__ __forceinline__ void finish(const StepArgs& a, const RepDev& R, int g) {
     const int nk = min(kept, KMAX);
     if (nk & 1) dst[(size_t)(nk >> 1) * ntot] = word;
-    sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell();
     if (kept > KMAX) flag(a.flags, ERR_OVERFLOW);
-    a.V[g] = 1.0f / (R.W0 + sw.value());
+    a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
     a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)nk);
     a.ncnt[g] = nk;
   }
@@ -336,6 +357,8 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
     const int vk = min(a.vcnt[g], KMAX);
     ExactSink<COMP, KERN> out;
     out.init(a, g);
+    // (no list prefetch here: the list stores below share the load counter,
+    // so waiting for a load issued early would also wait for those stores)
     const uint32_t* src = a.vl + g;
     for (int k = 0; k < vk; k += 2) {
       const uint32_t wd = src[(size_t)(k >> 1) * a.ntot];
@@ -366,7 +389,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
   __shared__ float2 s_off[MP];
   __shared__ float2 s_u[MP];
   __shared__ float2 s_q[MP];
-  __shared__ float s_V[MP];
+  __shared__ float s_V[MP];                  // V dWc: V_j F = s_V[j] Fr
   __shared__ float s_rho[FORM == 1 ? MP : 1];
   __shared__ float s_qc[Q3 == 1 ? MP : 1];   // Qyy of the quasi-2D variant
   RepDev R;
@@ -380,7 +403,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     s_u[t] = a.u[g];
     s_q[t] = a.q_cur[g];
     if constexpr (Q3 == 1) s_qc[t] = a.qyy_cur[g];
-    s_V[t] = a.V[g];
+    s_V[t] = a.V[g] * R.dWc;
     if constexpr (FORM == 1) s_rho[t] = R.rho0 + a.drho[g];
   }
   __syncthreads();
@@ -422,10 +445,9 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        const KW k = kernel_wf<KERN>(R, r2);
-        const float Vj = s_V[j];
+        const KW k = kernel_raw<KERN>(R, r2);
         const float2 uj = s_u[j], qj = s_q[j];
-        const float c = Vj * k.F;              // V_j W'(r)/r
+        const float c = s_V[j] * k.F;          // V_j W'(r)/r
         const float cx = c * rx, cy = c * ry;  // V_j grad_i W_ij
         const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
         Sxx.add(txx); Sxy.add(txy); Syy.add(tyy);
@@ -448,7 +470,8 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
           Vsx.fma(sv, cx); Vsy.fma(sv, cy);
         } else {
           const float rj = s_rho[j];
-          const float fx = k.F * rx, fy = k.F * ry;  // grad_i W_ij
+          const float Ft = R.dWc * k.F;
+          const float fx = Ft * rx, fy = Ft * ry;    // grad_i W_ij
           Kc.add(-(dux * fx + duy * fy));
           const float svr = sv / rj;
           V1x.fma(svr, fx); V1y.fma(svr, fy);
@@ -456,7 +479,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
           const float ca = qi.x * ri2inv + qj.x * rj2inv, cb = qi.y * ri2inv + qj.y * rj2inv;
           A1x.add(ca * fx + cb * fy); A1y.add(cb * fx - ca * fy);
         }
-        Wux.fma(-dux, k.W); Wuy.fma(-duy, k.W);
+        Wux.fma(-dux, k.W); Wuy.fma(-duy, k.W);   // in units of a2
       }, [&]() {
         Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell();
         Gxx.end_cell(); Gxy.end_cell(); Gyx.end_cell(); Gyy.end_cell();
@@ -568,7 +591,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         apy = cv * v1y - R.zeta * R.mass * a1y;
       }
       a.apart[g] = make_float2(apx, apy);
-      a.uv[g] = sqrtf(wux * wux + wuy * wuy) * s_V[p];
+      a.uv[g] = sqrtf(wux * wux + wuy * wuy) * (R.a2 * a.V[g]);
       if constexpr (EL == 1) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
@@ -627,7 +650,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        sd.fma(s_dh[j], kernel_w<KERN>(R, r2));
+        sd.fma(s_dh[j], kernel_raw<KERN>(R, r2).W);   // in units of a2
       }, [&]() { sd.end_cell(); });
     }
     const float tot = wave_sum(sd.value(), lpp);
@@ -635,7 +658,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       const float Vi = a.V[g];
       const float dhi = s_dh[p];
       // Shepard filter with the self term, written for rho - rho0
-      const float shep = Vi * fmaf(R.W0, dhi, tot);
+      const float shep = (Vi * R.a2) * fmaf(kernel_w0_raw<KERN>(), dhi, tot);
       const float drh = dhi - R.beta * (dhi - shep);
       const float x = drh * R.inv_rho0;
       float pw;  // (1 + x)^gamma - 1
@@ -656,6 +679,9 @@ template <int T, int COMP, int FORM, int EL, int KERN, int INTEG>
 __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   constexpr int MP = TileCfg<T, KERN>::MAXP;
+  // FORM 0 stages V dWc (V_j F = s_V[j] Fr); without the lambda stress it also
+  // stages s_P = P V dWc, so that (P_i + P_j) V_j F = (P_i s_V[j] + s_P[j]) Fr.
+  constexpr bool PV = FORM == 0 && EL == 0;
   __shared__ float2 s_off[MP];
   __shared__ float s_V[MP];
   __shared__ float s_P[MP];
@@ -669,8 +695,9 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
   for (int t = threadIdx.x; t < S; t += WG) {
     const int g = staged_global<T>(a, L, t);
     s_off[t] = a.off_cur[g];
-    s_V[t] = a.V[g];
-    s_P[t] = a.P[g];
+    const float Vd = a.V[g] * R.dWc;
+    s_V[t] = Vd;
+    s_P[t] = PV ? a.P[g] * Vd : a.P[g];
     if constexpr (EL == 1) s_pi[t] = a.pi[g];
   }
   __syncthreads();
@@ -694,16 +721,16 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
     float2 oi = {0.f, 0.f};
     if (act) {
       oi = s_off[p];
-      const float Pi = s_P[p];
+      const float Pi = PV ? a.P[g] : s_P[p];
       float2 pii = {0.f, 0.f};
       if constexpr (EL == 1) pii = s_pi[p];
       const int cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        const KW k = kernel_wf<KERN>(R, r2);
-        const float c = (FORM == 0) ? s_V[j] * k.F : k.F;
-        const float f = (Pi + s_P[j]) * c;
+        const KW k = kernel_raw<KERN>(R, r2);
+        const float c = (FORM == 0) ? s_V[j] * k.F : R.dWc * k.F;
+        const float f = PV ? fmaf(Pi, s_V[j], s_P[j]) * k.F : (Pi + s_P[j]) * c;
         Px.fma(f, rx); Py.fma(f, ry);
         if constexpr (EL == 1) {
           const float2 pj = s_pi[j];
