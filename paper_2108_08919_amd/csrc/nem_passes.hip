@@ -59,6 +59,12 @@ __device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int
 // The 32-bit words of one particle's list (two 16-bit entries each, rows
 // `stride` words apart), each loaded two words before it is used so that the
 // load's latency overlaps the pair work of the words before it.
+// CLAMP 0: rows past the particle's nw words are not loaded. CLAMP 1: every
+// load is issued (the same for every lane, so the compiler can wait for it a
+// whole iteration later even where the walk also stores): a row past the
+// particle's words is clamped to the last row of the list (KMAX/2 rows are
+// allocated for every particle) and its word is never used.
+template <int CLAMP>
 struct ListStream {
   const uint32_t* p;
   size_t stride;
@@ -66,13 +72,19 @@ struct ListStream {
   uint32_t w0, w1;
   __device__ __forceinline__ ListStream(const uint32_t* p_, size_t stride_, int nwords)
       : p(p_), stride(stride_), nw(nwords), m(2) {
-    w0 = nw > 0 ? p[0] : 0u;
-    w1 = nw > 1 ? p[stride] : 0u;
+    if (CLAMP) {
+      w0 = p[0];
+      w1 = p[stride];
+    } else {
+      w0 = nw > 0 ? p[0] : 0u;
+      w1 = nw > 1 ? p[stride] : 0u;
+    }
   }
   __device__ __forceinline__ uint32_t next() {
     const uint32_t w = w0;
     w0 = w1;
-    w1 = m < nw ? p[(size_t)m * stride] : 0u;
+    if (CLAMP) w1 = p[(size_t)min(m, KMAX / 2 - 1) * stride];
+    else w1 = m < nw ? p[(size_t)m * stride] : 0u;
     ++m;
     return w;
   }
@@ -86,7 +98,7 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
                                             int sub, Body&& body, Flush&& flush) {
   const uint32_t* p = nl + g;
   if (lpp == 1) {
-    ListStream ls(p, (size_t)ntot, (cnt + 1) >> 1);
+    ListStream<0> ls(p, (size_t)ntot, (cnt + 1) >> 1);
     int k = 0;
     for (; k + 1 < cnt; k += 2) {
       const uint32_t w = ls.next();
@@ -216,17 +228,23 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 // criterion as before.
 
 // The step's neighbour list of one particle under construction: accepted pairs
-// are summed (V, APD geometry) and appended as 16-bit entries.
+// are summed (V, APD geometry) and appended as 16-bit entries. Entries go
+// through a ring of RING words in this lane's column of an LDS buffer (word m
+// at lw[(m % RING) * WG]) that is copied to the list every 2 RING entries and
+// at the end, so that the walk issues its global stores in bursts: they share
+// the load counter with the list words the walk loads ahead.
+constexpr int RING = 8;
 template <int COMP, int KERN>
 struct ExactSink {
   Acc<COMP> sw, sx3, sy3, sr;
   int kept;
   uint32_t word;
+  uint32_t* lw;
   uint32_t* dst;
-  int64_t ntot;
-  __device__ __forceinline__ void init(const StepArgs& a, int g) {
+  size_t ntot;
+  __device__ __forceinline__ void init(uint32_t* lds_column, const StepArgs& a, int g) {
     sw.init(); sx3.init(); sy3.init(); sr.init();
-    kept = 0; word = 0u; dst = a.nl + g; ntot = a.ntot;
+    kept = 0; word = 0u; lw = lds_column; dst = a.nl + g; ntot = (size_t)a.ntot;
   }
   __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
     const KW kw = kernel_raw<KERN>(R, r2);
@@ -234,15 +252,21 @@ struct ExactSink {
     const float r3 = kw.rinv * kw.rinv * kw.rinv;
     sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(kw.r);
     if (kept < KMAX) {
-      if (kept & 1) dst[(size_t)(kept >> 1) * ntot] = word | (e << 16);
+      if (kept & 1) lw[((kept >> 1) % RING) * WG] = word | (e << 16);
       else word = e;
     }
     ++kept;
     if ((kept & 15) == 0) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
+    if ((kept & (2 * RING - 1)) == 0 && kept <= KMAX) {
+      const int m0 = (kept >> 1) - RING;
+#pragma unroll
+      for (int i = 0; i < RING; ++i) dst[(size_t)(m0 + i) * ntot] = lw[i * WG];
+    }
   }
   __device__ __forceinline__ void finish(const StepArgs& a, const RepDev& R, int g) {
     const int nk = min(kept, KMAX);
-    if (nk & 1) dst[(size_t)(nk >> 1) * ntot] = word;
+    if (nk & 1) lw[((nk >> 1) % RING) * WG] = word;
+    for (int m = (nk >> 1) / RING * RING; m < (nk + 1) >> 1; ++m) dst[(size_t)m * ntot] = lw[(m % RING) * WG];
     if (kept > KMAX) flag(a.flags, ERR_OVERFLOW);
     a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
     a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)nk);
@@ -258,6 +282,7 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
   __shared__ unsigned long long s_mask[9 * WG];
+  __shared__ uint32_t s_outw[RING * WG];   // step-list ring, lane-minor
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -305,7 +330,7 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
     ExactSink<COMP, KERN> out;
-    out.init(a, g);
+    out.init(s_outw + threadIdx.x, a, g);
     int c = -1;
     unsigned long long m = 0ull, x = 0ull;
     uint32_t vword = 0u;
@@ -339,6 +364,7 @@ template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
+  __shared__ uint32_t s_outw[RING * WG];   // step-list ring, lane-minor
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -356,12 +382,10 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
     const float2 oi = s_off[p];
     const int vk = min(a.vcnt[g], KMAX);
     ExactSink<COMP, KERN> out;
-    out.init(a, g);
-    // (no list prefetch here: the list stores below share the load counter,
-    // so waiting for a load issued early would also wait for those stores)
-    const uint32_t* src = a.vl + g;
+    out.init(s_outw + threadIdx.x, a, g);
+    ListStream<1> ls(a.vl + g, (size_t)a.ntot, (vk + 1) >> 1);
     for (int k = 0; k < vk; k += 2) {
-      const uint32_t wd = src[(size_t)(k >> 1) * a.ntot];
+      const uint32_t wd = ls.next();
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (k + h >= vk) break;
