@@ -62,8 +62,9 @@ __device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int
 // CLAMP 0: rows past the particle's nw words are not loaded. CLAMP 1: every
 // load is issued (the same for every lane, so the compiler can wait for it a
 // whole iteration later even where the walk also stores): a row past the
-// particle's words is clamped to the last row of the list (KMAX/2 rows are
-// allocated for every particle) and its word is never used.
+// particle's words is clamped to its last word's row (row 0 when the list is
+// empty; KMAX/2 rows are allocated for every particle), a cached re-read whose
+// word is never used.
 template <int CLAMP>
 struct ListStream {
   const uint32_t* p;
@@ -74,7 +75,7 @@ struct ListStream {
       : p(p_), stride(stride_), nw(nwords), m(2) {
     if (CLAMP) {
       w0 = p[0];
-      w1 = p[stride];
+      w1 = p[(size_t)min(1, max(nw - 1, 0)) * stride];
     } else {
       w0 = nw > 0 ? p[0] : 0u;
       w1 = nw > 1 ? p[stride] : 0u;
@@ -83,7 +84,7 @@ struct ListStream {
   __device__ __forceinline__ uint32_t next() {
     const uint32_t w = w0;
     w0 = w1;
-    if (CLAMP) w1 = p[(size_t)min(m, KMAX / 2 - 1) * stride];
+    if (CLAMP) w1 = p[(size_t)min(m, max(nw - 1, 0)) * stride];
     else w1 = m < nw ? p[(size_t)m * stride] : 0u;
     ++m;
     return w;
