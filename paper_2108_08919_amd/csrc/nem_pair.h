@@ -134,14 +134,20 @@ __device__ __forceinline__ KW kernel_raw(const RepDev& R, float r2) {
   k.rinv = __builtin_amdgcn_rsqf(r2);
   k.r = r2 * k.rinv;
   const float b = k.r * R.hinv;   // q
+  // (1 - q)_+ and (2 - q)_+ / 2 lie in [0, 1] (q >= 0), so each is one
+  // instruction with the result clamp. t2 = 2 u exactly (scaling by 2 commutes
+  // with rounding), so -6 t2^4 = -96 u^4 and -6 t2^5 = -192 u^4 u give the same
+  // bits as the unscaled form.
   if constexpr (KERN == 0) {
-    const float t3 = 3.0f - b, t2 = fmaxf(2.0f - b, 0.0f), t1 = fmaxf(1.0f - b, 0.0f);
-    const float t3s = t3 * t3, t2s = t2 * t2, t1s = t1 * t1;
-    const float t34 = t3s * t3s, t24 = t2s * t2s, t14 = t1s * t1s;
-    k.W = fmaf(15.0f * t14, t1, fmaf(-6.0f * t24, t2, t34 * t3));
-    k.F = fmaf(15.0f, t14, fmaf(-6.0f, t24, t34)) * k.rinv;
+    const float t3 = 3.0f - b;
+    const float u = fminf(fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f), 1.0f);   // (2 - q)_+ / 2
+    const float t1 = fminf(fmaxf(1.0f - b, 0.0f), 1.0f);               // (1 - q)_+
+    const float t3s = t3 * t3, us = u * u, t1s = t1 * t1;
+    const float t34 = t3s * t3s, u4 = us * us, t14 = t1s * t1s;
+    k.W = fmaf(15.0f * t14, t1, fmaf(-192.0f * u4, u, t34 * t3));
+    k.F = fmaf(15.0f, t14, fmaf(-96.0f, u4, t34)) * k.rinv;
   } else {
-    const float t = fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f);
+    const float t = fminf(fmaxf(fmaf(-0.5f, b, 1.0f), 0.0f), 1.0f);
     const float t2 = t * t;
     k.W = (t2 * t2) * fmaf(2.0f, b, 1.0f);
     k.F = t2 * t;

@@ -21,9 +21,10 @@
 //           velocity gradient and continuity (Eqs. sph1stDerivative,
 //           sphContinuity), Q gradient and Laplacian, molecular field
 //           (Eq. molecularfielddis), co-rotation (Eq. corotation), Q update
-//           (Eq. mi), viscous and active accelerations (Eq. sphMomentum), APD
-//           velocity variance (Eq. APD)
-//   pass C  density filter (Eq. densityCorrection) and EoS (Eq. sphEos)
+//           (Eq. mi), viscous and active accelerations (Eq. sphMomentum)
+//   pass C  density filter (Eq. densityCorrection) and EoS (Eq. sphEos); APD
+//           velocity variance (Eq. APD: u^{n+1/2} is the same as in pass B,
+//           and this pass evaluates W anyway)
 //   pass D  pressure term (Eq. sphMomentum), corrector, APD displacement
 //           (Eq. APD) and the next step's predictor (Sec. 3.1), fused
 #include <algorithm>
@@ -447,13 +448,13 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     const bool act = g >= 0;
     // raw pair sums (see the epilogue for their meaning)
     Acc<COMP> Sxx, Sxy, Syy, Gxx, Gxy, Gyx, Gyy, Qax, Qay, Qbx, Qby;
-    Acc<COMP> Mxx_a, Mxy_a, Myy_a, Mxx_b, Mxy_b, Myy_b, Vsx, Vsy, Wux, Wuy;
+    Acc<COMP> Mxx_a, Mxy_a, Myy_a, Mxx_b, Mxy_b, Myy_b, Vsx, Vsy;
     Acc<COMP> Kc, V1x, V1y, A1x, A1y;
     Acc<COMP> Qcx, Qcy, Mxx_c, Mxy_c, Myy_c;   // quasi-2D: gradient and Laplacian sums of Qyy
     Sxx.init(); Sxy.init(); Syy.init(); Gxx.init(); Gxy.init(); Gyx.init(); Gyy.init();
     Qax.init(); Qay.init(); Qbx.init(); Qby.init();
     Mxx_a.init(); Mxy_a.init(); Myy_a.init(); Mxx_b.init(); Mxy_b.init(); Myy_b.init();
-    Vsx.init(); Vsy.init(); Wux.init(); Wuy.init();
+    Vsx.init(); Vsy.init();
     Kc.init(); V1x.init(); V1y.init(); A1x.init(); A1y.init();
     Qcx.init(); Qcy.init(); Mxx_c.init(); Mxy_c.init(); Myy_c.init();
     float2 ui = {0.f, 0.f}, qi = {0.f, 0.f};
@@ -504,14 +505,13 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
           const float ca = qi.x * ri2inv + qj.x * rj2inv, cb = qi.y * ri2inv + qj.y * rj2inv;
           A1x.add(ca * fx + cb * fy); A1y.add(cb * fx - ca * fy);
         }
-        Wux.fma(-dux, k.W); Wuy.fma(-duy, k.W);   // in units of a2
       }, [&]() {
         Sxx.end_cell(); Sxy.end_cell(); Syy.end_cell();
         Gxx.end_cell(); Gxy.end_cell(); Gyx.end_cell(); Gyy.end_cell();
         Qax.end_cell(); Qay.end_cell(); Qbx.end_cell(); Qby.end_cell();
         Mxx_a.end_cell(); Mxy_a.end_cell(); Myy_a.end_cell();
         Mxx_b.end_cell(); Mxy_b.end_cell(); Myy_b.end_cell();
-        Vsx.end_cell(); Vsy.end_cell(); Wux.end_cell(); Wuy.end_cell();
+        Vsx.end_cell(); Vsy.end_cell();
         if constexpr (FORM == 1) { Kc.end_cell(); V1x.end_cell(); V1y.end_cell(); A1x.end_cell(); A1y.end_cell(); }
         if constexpr (Q3 == 1) { Qcx.end_cell(); Qcy.end_cell(); Mxx_c.end_cell(); Mxy_c.end_cell(); Myy_c.end_cell(); }
       });
@@ -525,7 +525,6 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
     const float myya = wave_sum(Myy_a.value(), lpp);
     const float mxxb = wave_sum(Mxx_b.value(), lpp), mxyb = wave_sum(Mxy_b.value(), lpp);
     const float myyb = wave_sum(Myy_b.value(), lpp);
-    const float wux = wave_sum(Wux.value(), lpp), wuy = wave_sum(Wuy.value(), lpp);
     float vsx = 0.f, vsy = 0.f, kc = 0.f, v1x = 0.f, v1y = 0.f, a1x = 0.f, a1y = 0.f;
     float qcx = 0.f, qcy = 0.f, mxxc = 0.f, mxyc = 0.f, myyc = 0.f;
     if constexpr (Q3 == 1) {
@@ -616,7 +615,6 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         apy = cv * v1y - R.zeta * R.mass * a1y;
       }
       a.apart[g] = make_float2(apx, apy);
-      a.uv[g] = sqrtf(wux * wux + wuy * wuy) * (R.a2 * a.V[g]);
       if constexpr (EL == 1) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
@@ -639,6 +637,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
   constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ float s_dh[MP];
+  __shared__ float2 s_u[MP];
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -648,6 +647,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
     const int g = staged_global<T>(a, L, t);
     s_off[t] = a.off_cur[g];
     s_dh[t] = a.dh[g];
+    s_u[t] = a.u[g];
   }
   __syncthreads();
   unsigned umb = 0;
@@ -667,18 +667,22 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); g = -1; }
     }
     const bool act = g >= 0;
-    Acc<COMP> sd;
-    sd.init();
+    Acc<COMP> sd, Wux, Wuy;   // in units of a2
+    sd.init(); Wux.init(); Wuy.init();
     if (act) {
-      const float2 oi = s_off[p];
+      const float2 oi = s_off[p], ui = s_u[p];
       const int cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        sd.fma(s_dh[j], kernel_raw<KERN>(R, r2).W);   // in units of a2
-      }, [&]() { sd.end_cell(); });
+        const float W = kernel_raw<KERN>(R, r2).W;
+        const float2 uj = s_u[j];
+        sd.fma(s_dh[j], W);
+        Wux.fma(ui.x - uj.x, W); Wuy.fma(ui.y - uj.y, W);   // sum_j (u_i - u_j) W_ij
+      }, [&]() { sd.end_cell(); Wux.end_cell(); Wuy.end_cell(); });
     }
     const float tot = wave_sum(sd.value(), lpp);
+    const float wux = wave_sum(Wux.value(), lpp), wuy = wave_sum(Wuy.value(), lpp);
     if (act && sub == 0) {
       const float Vi = a.V[g];
       const float dhi = s_dh[p];
@@ -694,6 +698,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
       const float rh = R.rho0 + drh;
       a.P[g] = pc * pw / (rh * rh);
       a.drhat[g] = drh;
+      a.uv[g] = sqrtf(wux * wux + wuy * wuy) * (R.a2 * Vi);
     }
   }
 }
