@@ -58,8 +58,10 @@ __device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int
 }
 
 // The 32-bit words of one particle's list (two 16-bit entries each, rows
-// `stride` words apart), each loaded two words before it is used so that the
-// load's latency overlaps the pair work of the words before it.
+// `stride` words apart), each loaded two words before it is used. The register
+// copy w0 = w1 makes the compiler wait for a load at the top of the next
+// iteration, so one iteration's pair work overlaps each load's latency (a
+// load waited for at once left the passes stalled on HBM).
 // CLAMP 0: rows past the particle's nw words are not loaded. CLAMP 1: every
 // load is issued (the same for every lane, so the compiler can wait for it a
 // whole iteration later even where the walk also stores): a row past the
