@@ -166,9 +166,9 @@ __device__ __forceinline__ void forward32(const WLds& W, ActF& a, int l, f32x4 y
 // NULL): max over samples of the Euclidean norm of the normalised output,
 // as float bits.
 //
-// Inference keeps everything in registers by computing each layer transposed,
-// H^T = W^T X^T: the weights are the A operand (preloaded once per wave as
-// fragments), the 16 samples of an iteration are the N dimension, and the
+// Inference keeps the activations in registers by computing each layer
+// transposed, H^T = W^T X^T: the weights are the A operand (fragments in LDS,
+// see FwdLds), the 16 samples of an iteration are the N dimension, and the
 // output tile D[4g + i][c] (g = l / 16, c = l % 16) holds hidden units
 // 16 mt + 4g + i of sample c. The next layer's B operand needs, in lane l,
 // K slots 8g..8g+7 of sample c; numbering the hidden units so that K slot
@@ -177,13 +177,70 @@ __device__ __forceinline__ void forward32(const WLds& W, ActF& a, int l, f32x4 y
 // weights' K index uses the same numbering), so no data moves between lanes.
 __device__ __forceinline__ int unit_of(int kc, int g, int i) { return 16 * (2 * kc + (i >> 2)) + 4 * g + (i & 3); }
 
+// Weight fragments of the inference kernel in LDS, shared by the workgroup's
+// four waves (per-wave register copies of all 5184 weights limited the kernel
+// to one or two waves per SIMD): fragment f of lane l at frag[f * 64 + l],
+// f = 0..3 layer 1 (m tile), 4..11 layer 2 (4 m tiles x 2 K tiles), 12..13
+// layer 3 (K tiles). Biases per lane as the four rows it holds, layers 1 and 2
+// pre-scaled by 2 log2(e) for the tanh below.
+struct FwdLds {
+  bf16x8 frag[14 * 64];
+  f32x4 b1[4 * 64], b2[4 * 64], b3[64];
+};
+constexpr float TANH_K = 2.8853900817779268f;   // 2 log2(e)
+
+// tanh(x) with x = d + bias and kb = TANH_K * bias (see fast_tanh)
+__device__ __forceinline__ float tanh_kb(float d, float kb) {
+  const float e = __builtin_amdgcn_exp2f(fmaf(TANH_K, d, kb));
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 // X rows are 48 bytes; VEC reads them as float4 (X 16-byte aligned).
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P, MlpNorm nm,
                                                      const float* __restrict__ X, int64_t n, float* Y,
                                                      unsigned* maxnorm) {
   constexpr int NB = 2;  // independent 16-sample blocks per iteration (instruction-level parallelism)
+  __shared__ FwdLds W;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+  // fill the fragments: A[m][k] = W^T, lane (gl, cl) holds k = 8 gl + i (in the
+  // unit numbering of unit_of for layers 2 and 3) of row m = 16 mt + cl
+  for (int t = threadIdx.x; t < 14 * 64; t += blockDim.x) {
+    const int f = t >> 6, ln = t & 63, gl = ln >> 4, cl = ln & 15;
+    bf16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float w;
+      if (f < 4) {
+        const int k = 8 * gl + i;
+        w = k < NI ? P[OFF_W1 + k * NH + 16 * f + cl] : 0.0f;
+      } else if (f < 12) {
+        const int mt = (f - 4) >> 1, kc = (f - 4) & 1;
+        w = P[OFF_W2 + unit_of(kc, gl, i) * NH + 16 * mt + cl];
+      } else {
+        w = cl < NO ? P[OFF_W3 + unit_of(f - 12, gl, i) * NO + cl] : 0.0f;
+      }
+      v[i] = (bf16)w;
+    }
+    W.frag[t] = v;
+  }
+  for (int t = threadIdx.x; t < 4 * 64; t += blockDim.x) {
+    const int mt = t >> 6, gl = (t & 63) >> 4;
+    f32x4 v1, v2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v1[i] = TANH_K * P[OFF_B1 + 16 * mt + 4 * gl + i];
+      v2[i] = TANH_K * P[OFF_B2 + 16 * mt + 4 * gl + i];
+    }
+    W.b1[t] = v1; W.b2[t] = v2;
+  }
+  for (int t = threadIdx.x; t < 64; t += blockDim.x) {
+    f32x4 v3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v3[i] = (4 * (t >> 4) + i < NO) ? P[OFF_B3 + 4 * (t >> 4) + i] : 0.0f;
+    W.b3[t] = v3;
+  }
+  __syncthreads();
   // this lane's input features 8g + i (i < nf) and their normalisation
   const int nf = g == 0 ? 8 : (g == 1 ? NI - 8 : 0);
   float xm8[8], xr8[8];
@@ -192,33 +249,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
     xm8[i] = i < nf ? nm.xm[8 * g + i] : 0.0f;
     xr8[i] = i < nf ? nm.xr[8 * g + i] : 0.0f;
   }
-  // weights as A fragments; biases as the accumulators' initial values
-  bf16x8 a1[4], a2[4][2], a3[2];
-  f32x4 b1[4], b2[4], b3;
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = 8 * g + i;
-      a1[mt][i] = (bf16)(k < NI ? P[OFF_W1 + k * NH + 16 * mt + c] : 0.0f);
-    }
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) a2[mt][kc][i] = (bf16)P[OFF_W2 + unit_of(kc, g, i) * NH + 16 * mt + c];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      b1[mt][i] = P[OFF_B1 + 16 * mt + 4 * g + i];
-      b2[mt][i] = P[OFF_B2 + 16 * mt + 4 * g + i];
-    }
-  }
-#pragma unroll
-  for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a3[kc][i] = (bf16)(c < NO ? P[OFF_W3 + unit_of(kc, g, i) * NO + c] : 0.0f);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) b3[i] = (4 * g + i < NO) ? P[OFF_B3 + 4 * g + i] : 0.0f;
-
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   float mx = 0.0f;
   const int64_t nblk = (n + 15) / 16;
   for (int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) * NB; b0 < nblk; b0 += (int64_t)gridDim.x * 4 * NB) {
@@ -247,37 +278,53 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
 #pragma unroll
       for (int i = 0; i < 8; ++i) xb[q][i] = (bf16)(keep * ((xv[i] - xm8[i]) * xr8[i]));
     }
+    // The fragment and bias reads below are the same every iteration; an
+    // empty asm statement on the lane index keeps the compiler from hoisting
+    // them out of the loop into registers (which would cost the occupancy the
+    // LDS copy is for).
+    int l_ = l;
+    asm volatile("" : "+v"(l_));
     f32x4 d[NB][4];
     bf16x8 hb[NB][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 a = W.frag[mt * 64 + l_];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a1[mt], xb[q], b1[mt]);
+      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a, xb[q], zero);
+    }
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
+    for (int kc = 0; kc < 2; ++kc) {
+      const f32x4 k0 = W.b1[(2 * kc) * 64 + l_], k1 = W.b1[(2 * kc + 1) * 64 + l_];
 #pragma unroll
-      for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          hb[q][kc][i] = (bf16)fast_tanh(d[q][2 * kc][i]);
-          hb[q][kc][4 + i] = (bf16)fast_tanh(d[q][2 * kc + 1][i]);
-        }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a2[mt][1], hb[q][1], mfma(a2[mt][0], hb[q][0], b2[mt]));
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-#pragma unroll
-      for (int kc = 0; kc < 2; ++kc)
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          hb[q][kc][i] = (bf16)fast_tanh(d[q][2 * kc][i]);
-          hb[q][kc][4 + i] = (bf16)fast_tanh(d[q][2 * kc + 1][i]);
+          hb[q][kc][i] = (bf16)tanh_kb(d[q][2 * kc][i], k0[i]);
+          hb[q][kc][4 + i] = (bf16)tanh_kb(d[q][2 * kc + 1][i], k1[i]);
         }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 a0 = W.frag[(4 + 2 * mt) * 64 + l_], a1 = W.frag[(5 + 2 * mt) * 64 + l_];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) d[q][mt] = mfma(a1, hb[q][1], mfma(a0, hb[q][0], zero));
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const f32x4 k0 = W.b2[(2 * kc) * 64 + l_], k1 = W.b2[(2 * kc + 1) * 64 + l_];
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[q][kc][i] = (bf16)tanh_kb(d[q][2 * kc][i], k0[i]);
+          hb[q][kc][4 + i] = (bf16)tanh_kb(d[q][2 * kc + 1][i], k1[i]);
+        }
+    }
+    const bf16x8 a30 = W.frag[12 * 64 + l_], a31 = W.frag[13 * 64 + l_];
+    const f32x4 b3 = W.b3[l_];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const f32x4 y = mfma(a3[1], hb[q][1], mfma(a3[0], hb[q][0], b3));
+      const f32x4 y = mfma(a31, hb[q][1], mfma(a30, hb[q][0], b3));
       // lane (g, c) holds outputs 4g + i of sample s: g = 0 -> 0..3, g = 1 -> 4
       float sq = 0.0f;
 #pragma unroll
