@@ -40,10 +40,10 @@ FP32_PEAK = 157.3e12     # FLOP/s, MI355X vector FP32 (packed FMA)
 # counter reads for a 1 GiB device-to-device copy in the same run (fetch x 2.0, write x 1.0). They hold
 # for the kernel sources with this fingerprint only; otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "fingerprint": "738817f4210321d7",
+    "fingerprint": "31c254d676e7cc56",
     "config": (2048, 4, 1, 1),
-    "bytes": {"pass_a_volume": 916.14e6, "pass_b_rates": 749.14e6, "pass_c_eos": 598.20e6,
-              "pass_d_update": 968.51e6},
+    "bytes": {"pass_a_volume": 849.03e6, "pass_b_rates": 749.13e6, "pass_c_eos": 598.20e6,
+              "pass_d_update": 901.03e6},
 }
 
 

@@ -102,7 +102,7 @@ struct Offs {
   size_t reps, work, cell_start, count, cursor, perm;
   size_t t_key, t_off, t_lo, t_u, t_q, t_drho, t_acc, t_id, t_img, t_qyy;
   size_t off0, off1, offlo, u, q0, q1, drho, acc, id, cell, img, qyy0, qyy1;
-  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, apdg, fe, vl, vcnt, off_build;
+  size_t V, bk, dh, apart, uv, pi, P, drhat, flags, umax, stage, red, nl, ncnt, fe, vl, vcnt, off_build;
   size_t total;
 };
 
@@ -151,7 +151,6 @@ Offs layout(int R, int64_t ntot, int64_t ncells, int64_t work_cap, int64_t stage
   o.umax = L.put(sizeof(unsigned) * 2 * R * UMAX_SLOTS);
   o.nl = L.put(sizeof(uint32_t) * (KMAX / 2) * N);
   o.ncnt = L.put(sizeof(int) * N);
-  o.apdg = L.put(sizeof(float4) * N);
   o.fe = L.put(sizeof(double) * 2 * N);
   o.vl = L.put(sizeof(uint32_t) * (KMAX / 2) * N);
   o.vcnt = L.put(sizeof(int) * N);
@@ -213,7 +212,7 @@ StepArgs step_args(nem_sim* s) {
   a.V = s->V; a.bk = s->bk; a.dh = s->dh; a.apart = s->apart; a.uv = s->uv; a.pi = s->pi;
   a.P = s->P; a.drhat = s->drhat; a.flags = s->flags;
   a.umax_cur = s->umax + (size_t)c * s->R * UMAX_SLOTS; a.umax_nxt = s->umax + (size_t)x * s->R * UMAX_SLOTS;
-  a.nl = s->nl; a.ncnt = s->ncnt; a.apdg = s->apdg;
+  a.nl = s->nl; a.ncnt = s->ncnt;
   a.feat = s->feat; a.id = s->id;
   a.vl = s->vl; a.vcnt = s->vcnt; a.off_build = s->off_build;
   return a;
@@ -500,7 +499,7 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   s->P = (float*)(b + o.P); s->drhat = (float*)(b + o.drhat);
   s->flags = (unsigned*)(b + o.flags); s->umax = (unsigned*)(b + o.umax);
   s->stage = (double*)(b + o.stage); s->red = (double*)(b + o.red);
-  s->nl = (uint32_t*)(b + o.nl); s->ncnt = (int*)(b + o.ncnt); s->apdg = (float4*)(b + o.apdg);
+  s->nl = (uint32_t*)(b + o.nl); s->ncnt = (int*)(b + o.ncnt);
   s->fe = (double*)(b + o.fe);
   s->vl = (uint32_t*)(b + o.vl); s->vcnt = (int*)(b + o.vcnt); s->off_build = (float2*)(b + o.off_build);
 

@@ -82,7 +82,6 @@ struct StepArgs {
   uint32_t* nl;              // neighbour list: word w of particle g at nl[w*ntot + g],
                              // two 16-bit entries (LDS slot | (dx+1)<<12 | (dy+1)<<14)
   int* ncnt;                 // accepted neighbours per particle
-  float4* apdg;              // APD geometry: (sum rx/r^3, sum ry/r^3, sum r, count)
   float* feat;               // NULL, or 12 features per particle at [g] (storage order)
   uint32_t* vl;              // Verlet list (pairs within the Verlet radius), layout as nl
   int* vcnt;                 // Verlet list length

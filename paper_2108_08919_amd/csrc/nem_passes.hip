@@ -16,7 +16,7 @@
 // of particles is spread over more lanes.
 //
 //   pass A  neighbour list; volume V_i = 1 / sum_j W_ij (Eq. sphSum, self
-//           included); APD geometry sums (Eq. APD)
+//           included)
 //   pass B  correction tensor and B = alpha^{-1} (Eq. sphCorrectionMatrix),
 //           velocity gradient and continuity (Eqs. sph1stDerivative,
 //           sphContinuity), Q gradient and Laplacian, molecular field
@@ -25,8 +25,9 @@
 //   pass C  density filter (Eq. densityCorrection) and EoS (Eq. sphEos); APD
 //           velocity variance (Eq. APD: u^{n+1/2} is the same as in pass B,
 //           and this pass evaluates W anyway)
-//   pass D  pressure term (Eq. sphMomentum), corrector, APD displacement
-//           (Eq. APD) and the next step's predictor (Sec. 3.1), fused
+//   pass D  pressure term (Eq. sphMomentum), corrector, APD geometry sums and
+//           displacement (Eq. APD) and the next step's predictor (Sec. 3.1),
+//           fused
 #include <algorithm>
 
 #include "nem_dev.h"
@@ -184,8 +185,8 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
-    Acc<COMP> sw, sx3, sy3, sr;
-    sw.init(); sx3.init(); sy3.init(); sr.init();
+    Acc<COMP> sw;
+    sw.init();
     int c = -1;
     unsigned long long m = 0ull, x = 0ull;
     uint32_t word = 0u;
@@ -203,18 +204,14 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
       const float2 oj = s_off[j];
       float rx, ry, r2;
       pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2);
-      const KW kw = kernel_raw<KERN>(R, r2);
-      sw.add(kw.W);
-      const float r3 = kw.rinv * kw.rinv * kw.rinv;
-      sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(kw.r);
+      sw.add(kernel_raw<KERN>(R, r2).W);
       const uint32_t e = (uint32_t)j | (hi & 0xF000u);
       if (k & 1) dst[(size_t)(k >> 1) * a.ntot] = word | (e << 16);
       else word = e;
-      if ((k & 15) == 15) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
+      if ((k & 15) == 15) sw.end_cell();
     }
     if (kept & 1) dst[(size_t)(kept >> 1) * a.ntot] = word;
     a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
-    a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)kept);
     a.ncnt[g] = kept;
   }
 }
@@ -232,7 +229,7 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 // criterion as before.
 
 // The step's neighbour list of one particle under construction: accepted pairs
-// are summed (V, APD geometry) and appended as 16-bit entries. Entries go
+// are summed (V) and appended as 16-bit entries. Entries go
 // through a ring of RING words in this lane's column of an LDS buffer (word m
 // at lw[(m % RING) * WG]) that is copied to the list every 2 RING entries and
 // at the end, so that the walk issues its global stores in bursts: they share
@@ -240,27 +237,24 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 constexpr int RING = 8;
 template <int COMP, int KERN>
 struct ExactSink {
-  Acc<COMP> sw, sx3, sy3, sr;
+  Acc<COMP> sw;
   int kept;
   uint32_t word;
   uint32_t* lw;
   uint32_t* dst;
   size_t ntot;
   __device__ __forceinline__ void init(uint32_t* lds_column, const StepArgs& a, int g) {
-    sw.init(); sx3.init(); sy3.init(); sr.init();
+    sw.init();
     kept = 0; word = 0u; lw = lds_column; dst = a.nl + g; ntot = (size_t)a.ntot;
   }
   __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
-    const KW kw = kernel_raw<KERN>(R, r2);
-    sw.add(kw.W);
-    const float r3 = kw.rinv * kw.rinv * kw.rinv;
-    sx3.fma(rx, r3); sy3.fma(ry, r3); sr.add(kw.r);
+    sw.add(kernel_raw<KERN>(R, r2).W);
     if (kept < KMAX) {
       if (kept & 1) lw[((kept >> 1) % RING) * WG] = word | (e << 16);
       else word = e;
     }
     ++kept;
-    if ((kept & 15) == 0) { sw.end_cell(); sx3.end_cell(); sy3.end_cell(); sr.end_cell(); }
+    if ((kept & 15) == 0) sw.end_cell();
     if ((kept & (2 * RING - 1)) == 0 && kept <= KMAX) {
       const int m0 = (kept >> 1) - RING;
 #pragma unroll
@@ -273,7 +267,6 @@ struct ExactSink {
     for (int m = (nk >> 1) / RING * RING; m < (nk + 1) >> 1; ++m) dst[(size_t)m * ntot] = lw[(m % RING) * WG];
     if (kept > KMAX) flag(a.flags, ERR_OVERFLOW);
     a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
-    a.apdg[g] = make_float4(sx3.value(), sy3.value(), sr.value(), (float)nk);
     a.ncnt[g] = nk;
   }
 };
@@ -749,14 +742,17 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
     }
     const bool act = g >= 0;
     Acc<COMP> Px, Py, Exx, Exy, Eyx, Eyy;
+    Acc<COMP> Gx, Gy, Gr;   // APD geometry: sum r_ij / r^3, sum r
     Px.init(); Py.init(); Exx.init(); Exy.init(); Eyx.init(); Eyy.init();
+    Gx.init(); Gy.init(); Gr.init();
     float2 oi = {0.f, 0.f};
+    int cnt = 0;
     if (act) {
       oi = s_off[p];
       const float Pi = PV ? a.P[g] : s_P[p];
       float2 pii = {0.f, 0.f};
       if constexpr (EL == 1) pii = s_pi[p];
-      const int cnt = min(a.ncnt[g], KMAX);
+      cnt = min(a.ncnt[g], KMAX);
       each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
@@ -764,6 +760,8 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
         const float c = (FORM == 0) ? s_V[j] * k.F : R.dWc * k.F;
         const float f = PV ? fmaf(Pi, s_V[j], s_P[j]) * k.F : (Pi + s_P[j]) * c;
         Px.fma(f, rx); Py.fma(f, ry);
+        const float r3 = k.rinv * k.rinv * k.rinv;
+        Gx.fma(rx, r3); Gy.fma(ry, r3); Gr.add(k.r);
         if constexpr (EL == 1) {
           const float2 pj = s_pi[j];
           const float cx = c * rx, cy = c * ry;
@@ -771,11 +769,12 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
           Exx.fma(dpa, cx); Exy.fma(dpa, cy); Eyx.fma(dpb, cx); Eyy.fma(dpb, cy);
         }
       }, [&]() {
-        Px.end_cell(); Py.end_cell();
+        Px.end_cell(); Py.end_cell(); Gx.end_cell(); Gy.end_cell(); Gr.end_cell();
         if constexpr (EL == 1) { Exx.end_cell(); Exy.end_cell(); Eyx.end_cell(); Eyy.end_cell(); }
       });
     }
     const float prx = wave_sum(Px.value(), lpp), pry = wave_sum(Py.value(), lpp);
+    const float gx = wave_sum(Gx.value(), lpp), gy = wave_sum(Gy.value(), lpp), gr = wave_sum(Gr.value(), lpp);
     float exx = 0.f, exy = 0.f, eyx = 0.f, eyy = 0.f;
     if constexpr (EL == 1) {
       exx = wave_sum(Exx.value(), lpp); exy = wave_sum(Exy.value(), lpp);
@@ -811,11 +810,10 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
         u1y = (uh.y - hdt * ap.y) + R.dt * ay;
       }
       float drx = 0.f, dry = 0.f;
-      const float4 ag = a.apdg[g];  // sum rx/r^3, sum ry/r^3, sum r, count
-      if (R.apd && ag.w > 0.0f) {
-        const float r0 = ag.z / ag.w;
+      if (R.apd && cnt > 0) {
+        const float r0 = gr / (float)cnt;   // mean neighbour distance
         const float f = r0 * r0 * a.uv[g] * R.dt;
-        drx = f * ag.x; dry = f * ag.y;
+        drx = f * gx; dry = f * gy;
       }
       const float unx = u1x + hdt * ax, uny = u1y + hdt * ay;      // u^{n+3/2}
       // r^{n+1} - r^{n+1/2}: u^{n+1} dt/2 (kick-drift-kick) or u^{n+1/2} dt/2

@@ -34,7 +34,7 @@ struct nem_sim {
   float* V = nullptr; float4* bk = nullptr; float* dh = nullptr; float2* apart = nullptr;
   float* uv = nullptr; float2* pi = nullptr; float* P = nullptr; float* drhat = nullptr;
   unsigned* flags = nullptr; unsigned* umax = nullptr;
-  uint32_t* nl = nullptr; int* ncnt = nullptr; float4* apdg = nullptr; double* fe = nullptr;
+  uint32_t* nl = nullptr; int* ncnt = nullptr; double* fe = nullptr;
   uint32_t* vl = nullptr; int* vcnt = nullptr; float2* off_build = nullptr;  // Verlet list
   double* stage = nullptr; int64_t stage_n = 0;
   double* red = nullptr;
