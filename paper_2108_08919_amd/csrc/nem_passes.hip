@@ -381,12 +381,14 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
     ExactSink<COMP, KERN> out;
     out.init(s_outw + threadIdx.x, a, g);
     ListStream<1> ls(a.vl + g, (size_t)a.ntot, (vk + 1) >> 1);
-    for (int k = 0; k < vk; k += 2) {
-      const uint32_t wd = ls.next();
+    for (int k = 0; k < vk; k += 4) {   // two words per iteration: more work behind each load
+      const uint32_t wa = ls.next();
+      const uint32_t wb = ls.next();
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 4; ++h) {
         if (k + h >= vk) break;
-        const uint32_t e = h ? (wd >> 16) : (wd & 0xFFFFu);
+        const uint32_t wd = h < 2 ? wa : wb;
+        const uint32_t e = (h & 1) ? (wd >> 16) : (wd & 0xFFFFu);
         const int j = min((int)(e & 0xFFFu), S - 1);
         const float2 sh = L.shift[(e >> 12) & 15u];
         const float2 oj = s_off[j];
