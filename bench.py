@@ -40,10 +40,10 @@ FP32_PEAK = 157.3e12     # FLOP/s, MI355X vector FP32 (packed FMA)
 # counter reads for a 1 GiB device-to-device copy in the same run (fetch x 2.0, write x 1.0). They hold
 # for the kernel sources with this fingerprint only; otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "fingerprint": "eb88555ffe2c03fb",
+    "fingerprint": "7dd2b5d08616ab78",
     "config": (2048, 4, 1, 1),
-    "bytes": {"pass_a_volume": 849.08e6, "pass_b_rates": 749.15e6, "pass_c_eos": 598.20e6,
-              "pass_d_update": 901.03e6},
+    "bytes": {"pass_a_volume": 849.06e6, "pass_b_rates": 749.13e6, "pass_c_eos": 598.10e6,
+              "pass_d_update": 901.06e6},
 }
 
 

@@ -98,13 +98,26 @@ struct ListStream {
 // Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
 // sub, sub+lpp, ...; flush() closes a compensation chunk every 16 pairs (the
 // last, open chunk is summed by the accumulators' value()).
-template <typename Body, typename Flush>
+// WPI: list words per iteration of the one-lane walk (2 puts four pairs of
+// work behind each load; the chunking of the compensated sums is the same).
+template <int WPI = 1, typename Body, typename Flush>
 __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int ntot, int g, int cnt, int lpp,
                                             int sub, Body&& body, Flush&& flush) {
   const uint32_t* p = nl + g;
   if (lpp == 1) {
     ListStream<0> ls(p, (size_t)ntot, (cnt + 1) >> 1);
     int k = 0;
+    if constexpr (WPI == 2) {
+      for (; k + 3 < cnt; k += 4) {
+        const uint32_t wa = ls.next();
+        const uint32_t wb = ls.next();
+        body(wa & 0xFFFFu);
+        body(wa >> 16);
+        body(wb & 0xFFFFu);
+        body(wb >> 16);
+        if ((k & 15) == 12) flush();
+      }
+    }
     for (; k + 1 < cnt; k += 2) {
       const uint32_t w = ls.next();
       body(w & 0xFFFFu);
@@ -669,7 +682,7 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
     if (act) {
       const float2 oi = s_off[p], ui = s_u[p];
       const int cnt = min(a.ncnt[g], KMAX);
-      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      each_listed<2>(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
         const float W = kernel_raw<KERN>(R, r2).W;
