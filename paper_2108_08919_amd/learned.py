@@ -144,7 +144,9 @@ def _observe(sim, side):
 def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0), dt=1e-3, mult=4, every=0.1):
     """Plain dt, plain mult*dt and learned mult*dt from the same seeded starts.
     All three observe at the same times: the start of the averaging window and
-    every `every` after it, both rounded to whole macro steps of mult*dt."""
+    every `every` after it, both rounded to whole macro steps of mult*dt. The
+    speedups are timed separately, each method over the whole horizon in one
+    call (the interleaved timings of the observed runs are reported too)."""
     import torch
     import workloads as wl
     p = wl.Params(L=float(side), zeta=0.02, K=0.02, dt=dt)
@@ -205,9 +207,54 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
         if mode in ferr:
             out[mode]["q_field_err"] = float(np.mean(ferr[mode]["q"]))
             out[mode]["u_field_err"] = float(np.mean(ferr[mode]["u"]))
-    out["speedup_learned_vs_plain"] = times["plain"] / times["learned"] if times["learned"] > 0 else None
-    out["speedup_coarse_vs_plain"] = times["plain"] / times["plain_coarse"] if times["plain_coarse"] > 0 else None
+    # Speed: each method over the whole horizon from seed 0's start, as one
+    # call with one synchronisation (the runs above synchronise at every
+    # observation; at large multipliers a span is a few macro steps and that
+    # overhead is a sizeable share of it), after one untimed macro step; the
+    # median of three runs.
+    k_total = sum(spans)
+    st0 = wl.initial_state(side, 1.0, 1.0, seed=3000 + seeds[0], kind="isotropic")
+    wall = {}
+    fallbacks_timed = 0
+    for mode in ("plain", "plain_coarse", "learned"):
+        q = p if mode != "plain_coarse" else p.replace(dt=mult * dt)
+        sim = _sim([q], [n])
+
+        def run(k):
+            if mode == "plain":
+                sim.step(k * mult)
+                sim.sync()
+                return 0
+            if mode == "plain_coarse":
+                sim.step(k)
+                sim.sync()
+                return 0
+            return sim.step_learned(m, k, mult, tau)[0]
+
+        sim.set_state(0, st0)
+        run(1)
+        reps = []
+        for _ in range(3):                       # median of three
+            sim.set_state(0, st0)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            nfb = run(k_total)
+            torch.cuda.synchronize()
+            reps.append(time.perf_counter() - c0)
+            if mode == "learned":
+                fallbacks_timed += nfb
+        wall[mode] = sorted(reps)[1]
+        sim.check()
+        sim.close()
+        _log(f"timed {mode} over {k_total} macro steps: " + " ".join(f"{t:.4f}" for t in reps) + " s")
+    out["seconds_uninterrupted"] = wall
+    out["speedup_learned_vs_plain"] = wall["plain"] / wall["learned"] if wall["learned"] > 0 else None
+    out["speedup_coarse_vs_plain"] = wall["plain"] / wall["plain_coarse"] if wall["plain_coarse"] > 0 else None
+    out["speedup_learned_vs_plain_interleaved"] = times["plain"] / times["learned"] if times["learned"] > 0 else None
+    out["speedup_coarse_vs_plain_interleaved"] = (times["plain"] / times["plain_coarse"]
+                                                  if times["plain_coarse"] > 0 else None)
     out["fallbacks"] = fallbacks
+    out["fallbacks_timed"] = fallbacks_timed
     out["tau"] = tau
     return out
 
