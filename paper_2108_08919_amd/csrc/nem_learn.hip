@@ -130,7 +130,10 @@ __global__ void k_sub(float* T, const float* C, int64_t n) {
 // norm (maxnorm, float bits) exceeds tau (bits of a positive float, so the
 // unsigned comparison orders them as floats).
 __global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, unsigned* umax_cur,
-                                                 const unsigned* maxnorm, unsigned tau_bits) {
+                                                 const unsigned* maxnorm, unsigned tau_bits, unsigned* host_norm) {
+  // the norm for the host's fallback decision, stored straight into pinned
+  // host memory (a plain vector store, visible once the kernel has completed)
+  if (host_norm && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *host_norm = maxnorm ? *maxnorm : 0u;
   if (maxnorm && *maxnorm > tau_bits) return;  // the macro step will be replayed as fine steps
   const int r = blockIdx.y;
   const RepDev& R = s.reps[r];
@@ -163,6 +166,13 @@ __global__ __launch_bounds__(256) void k_correct(SortArgs s, const float* Y, uns
     relist |= moved_too_far(s, R, k, nh);
   }
   block_speed_max(s, umax_cur, r, vmax, relist);
+}
+
+// Before the inference of a learned macro step: clear the largest-norm word
+// and the max-speed slots that k_correct refills (one launch, no memset).
+__global__ void k_learn_clear(unsigned* norm, unsigned* umax, int n_umax) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *norm = 0u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_umax; i += gridDim.x * blockDim.x) umax[i] = 0u;
 }
 
 // dst[(part_base + id) * w + c] = src[k * w + c]: rows from storage order to
@@ -599,11 +609,15 @@ int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, doub
   chk(hipMalloc((void**)&X, sizeof(float) * 12 * N), "hipMalloc (inputs)");
   chk(hipMalloc((void**)&Y, sizeof(float) * 5 * N), "hipMalloc (corrections)");
   chk(hipMalloc((void**)&mx, sizeof(unsigned) * 2), "hipMalloc (max norm)");
-  chk(hipHostMalloc((void**)&hmx, sizeof(unsigned) * 2, hipHostMallocDefault), "hipHostMalloc (max norm)");
+  chk(hipHostMalloc((void**)&hmx, sizeof(unsigned) * 2, hipHostMallocMapped | hipHostMallocCoherent),
+      "hipHostMalloc (max norm)");
+  unsigned* dmx = nullptr;   // the device's address of hmx
+  if (hmx) chk(hipHostGetDevicePointer((void**)&dmx, hmx, 0), "hipHostGetDevicePointer");
   for (auto& e : ev) chk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
   // One macro step, enqueued without waiting: snapshot, a step of mult*dt with
-  // the inputs captured, inference, the largest correction norm copied to the
-  // host, and the correction (skipped on the device when that norm exceeds tau).
+  // the inputs captured, inference, and the correction (skipped on the device
+  // when the largest correction norm exceeds tau), which also stores that norm
+  // in pinned host memory for the host's fallback decision.
   auto enqueue = [&](int64_t k) -> int {
     const int b = (int)(k & 1);
     int e = take_snapshot(s, b);
@@ -612,17 +626,14 @@ int nem_step_learned(nem_sim* s, nem_mlp* m, int64_t n_macro, int32_t mult, doub
     e = run_steps(s, 1);
     s->feat = nullptr;
     if (e) return e;
-    if (!chk(hipMemsetAsync(mx + b, 0, sizeof(unsigned), s->stream), "hipMemsetAsync")) return rc;
-    launch_mlp_forward(m->P, m->hnorm, X, (int64_t)N, Y, mx + b, s->stream);
-    if (!chk(hipMemcpyAsync(hmx + b, mx + b, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync"))
-      return rc;
-    if (!chk(hipEventRecord(ev[b], s->stream), "hipEventRecord")) return rc;
     unsigned* um = s->umax + (size_t)s->parity * s->R * UMAX_SLOTS;
-    if (!chk(hipMemsetAsync(um, 0, sizeof(unsigned) * s->R * UMAX_SLOTS, s->stream), "hipMemsetAsync")) return rc;
+    hipLaunchKernelGGL(k_learn_clear, dim3(1), dim3(256), 0, s->stream, mx + b, um, s->R * UMAX_SLOTS);
+    launch_mlp_forward(m->P, m->hnorm, X, (int64_t)N, Y, mx + b, s->stream);
     SortArgs a = sort_args(s, nullptr);
     hipLaunchKernelGGL(k_correct, rep_grid(s), dim3(256), 0, s->stream, a, (const float*)Y, um,
-                       (const unsigned*)(mx + b), tau_bits);
-    chk(hipGetLastError(), "k_correct");
+                       (const unsigned*)(mx + b), tau_bits, dmx + b);
+    if (!chk(hipGetLastError(), "k_correct")) return rc;
+    if (!chk(hipEventRecord(ev[b], s->stream), "hipEventRecord")) return rc;
     return rc;
   };
   int64_t nfb = 0;
