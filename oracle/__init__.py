@@ -59,6 +59,8 @@ def lib():
         L.orc_molecular_field3.argtypes = [C.POINTER(OrcParams), dp, dp, dp]
         L.orc_molecular_field.restype = None
         L.orc_molecular_field.argtypes = [C.POINTER(OrcParams), dp, dp, dp]
+        L.orc_elastic_stress.restype = None
+        L.orc_elastic_stress.argtypes = [C.c_double, dp, dp, dp]
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcState), C.c_int64, C.POINTER(OrcDiag)]
         L.orc_diagnostics.restype = C.c_int
@@ -243,6 +245,15 @@ def molecular_field(params, Q, lapQ):
     cp = make_params(params)
     lib().orc_molecular_field(C.byref(cp), _dp(Q), _dp(lq), _dp(H))
     return H.reshape(2, 2)
+
+
+def elastic_stress(lam: float, Q, H):
+    """lambda part of the elastic stress (2x2) for Q and H (2x2 each)."""
+    Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(4))
+    H = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(4))
+    Pi = np.zeros(4)
+    lib().orc_elastic_stress(lam, _dp(Q), _dp(H), _dp(Pi))
+    return Pi.reshape(2, 2)
 
 
 def deposit(params, x, y, fields, M: int):

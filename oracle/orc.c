@@ -126,6 +126,17 @@ void orc_molecular_field(const orc_params* p, const double* Q, const double* lap
     H[k] = -p->A * Q[k] + p->B * (Q2[k] - 0.5 * t * I[k]) - p->C * Q[k] * t + p->K * lapQ[k];
 }
 
+/* lambda terms of Eq. elasticstress with D = Q + I/2 and the parenthesis closed
+ * after Q:H, written as the literal matrix products:
+ * Pi = 2 lam D (Q:H) - lam H D - lam D H. */
+void orc_elastic_stress(double lam, const double* Q, const double* H, double* Pi) {
+  double D[4] = {Q[0] + 0.5, Q[1], Q[2], Q[3] + 0.5}, HD[4], DH[4];
+  mm(H, D, HD);
+  mm(D, H, DH);
+  double qh = ddot(Q, H);
+  for (int c = 0; c < 4; ++c) Pi[c] = 2.0 * lam * D[c] * qh - lam * HD[c] - lam * DH[c];
+}
+
 /* ------------------------------------------------------------ 3x3 algebra */
 /* Row-major 3x3, quasi-2D variant: the flow is in the plane (no u_z, no z
  * dependence), Q is a full 3x3 tensor and the identity is I/3 as printed. */
@@ -616,12 +627,8 @@ static int eval_rates(const orc_params* p, const orc_state* s, const double* xh,
     double mp[4] = {mr[0] - t, off, off, mr[3] - t};
     memcpy(w->H + 4 * i, H, sizeof(H));
     for (int c = 0; c < 4; ++c) w->qn[4 * i + c] = Qi[c] + mp[c] * dt;
-    /* lambda terms of Eq. elasticstress with D = Q + I/2 (parenthesis closed
-     * after Q:H): Pi = 2 lam D (Q:H) - lam H D - lam D H */
-    double D[4] = {Qi[0] + 0.5, Qi[1], Qi[2], Qi[3] + 0.5}, HD[4], DH[4];
-    mm(H, D, HD); mm(D, H, DH);
-    double qh = ddot(Qi, H);
-    for (int c = 0; c < 4; ++c) w->Pi[4 * i + c] = 2.0 * p->lam * D[c] * qh - p->lam * HD[c] - p->lam * DH[c];
+    /* lambda terms of Eq. elasticstress (literal matrix products) */
+    orc_elastic_stress(p->lam, Qi, H, w->Pi + 4 * i);
   }
 
   /* Eq. sphMomentum at the half step, with rho_hat for rho, eta = nu rho0 and

@@ -83,6 +83,10 @@ void orc_corotation(double lam, const double* Q, const double* G, double* S);
 /* Molecular field (Eq. molecularfielddis with d = 2) for Q (4), lapQ (4). */
 void orc_molecular_field(const orc_params* p, const double* Q, const double* lapQ, double* H);
 
+/* lambda part of the elastic stress (Eq. elasticstress with d = 2, D = Q + I/2):
+ * Pi = 2 lam D (Q:H) - lam H D - lam D H, as literal 2x2 matrix products. */
+void orc_elastic_stress(double lam, const double* Q, const double* H, double* Pi);
+
 /* Equation of state (Eq. sphEos). */
 double orc_eos(double rho, double rho0, double c0, double gamma_eos);
 
