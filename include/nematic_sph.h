@@ -41,8 +41,8 @@ extern "C" {
 #define NEM_E_NUMERIC (-4)   /* a non-finite value appeared in the state */
 #define NEM_E_OVERFLOW (-5)  /* a cell tile exceeds the LDS staging capacity (on average 24 particles
                                 per cell of the quintic spline, 10 per cell of Wendland C2), a cell
-                                holds more than 48 particles, or a particle has more than 64
-                                neighbours */
+                                holds more than 48 particles, or a particle has more than 96
+                                pairs within the Verlet radius kappa h + 0.075 h */
 #define NEM_E_SINGULAR (-6)  /* correction tensor not invertible; B = I was used */
 #define NEM_E_STATE (-7)     /* call order (e.g. step before set_state) */
 #define NEM_E_RANGE (-8)     /* an index fell outside its buffer; the access was skipped */
@@ -139,17 +139,38 @@ int nem_step(nem_sim* s, int64_t nsteps);
 /* Wait for the stream; return the first sticky device error (and clear nothing). */
 int nem_sync(nem_sim* s);
 
-/* Neighbour lists of replica r at the configuration the next step searches
- * (r^{n+1/2}), in CSR by particle id with ascending columns. The GPU keeps no
- * list: this enumerates pairs with the kernels' own predicate. Positions are
- * FP32 offsets o from the corner of the particle's cell (cells of side
- * cs = fl32(L/nc), nc = floor(L/(kappa h + skin))); for j in the cell displaced by
- * d in {-1,0,1}^2 from i's cell, r = fl(fl(o_i - o_j) + fl32(-d cs)) per
- * component, r2 = fl(fl(rx*rx) + fl(ry*ry)) without fused multiply-add, and j
- * is a neighbour when 0 < r2 < fl32((kappa h)^2) (Eq. quintic: support 3h; 2h
- * for the Wendland C2 variant).
+/* Neighbour lists of replica r as the next step's pair passes walk them, at
+ * the configuration that step uses (r^{n+1/2}), in CSR by particle id with
+ * ascending columns (Eq. quintic: neighbours are the particles within the
+ * kernel support 3h; 2h for the Wendland C2 variant).
+ *
+ * The library keeps a Verlet list per particle: every pair of the 3 x 3 cell
+ * stencil closer than kappa h + delta (delta = 0.075 h) when it was last built;
+ * it is rebuilt on the device when some particle has moved 0.45 delta since,
+ * after a rebin, a new state, a tile change or a snapshot restore. Every pair
+ * pass (volume, rates, filter, stress) walks that list and keeps an entry when
+ * 0 < r2 < fl32((kappa h)^2), where, with positions held as FP32 offsets o from
+ * the corner of the particle's cell (cells of side cs = fl32(L/nc),
+ * nc = floor(L/(kappa h + skin))) and j in the cell displaced by d in
+ * {-1,0,1}^2 from i's cell, r = fl(fl(o_i - o_j) + fl32(-d cs)) per component
+ * and r2 = fl(fl(rx*rx) + fl(ry*ry)), without fused multiply-add.
+ *
+ * This call first runs the start of the next step on the stream (the rebin if
+ * one is pending, the decision to rebuild, and the Verlet build or walk of the
+ * volume pass; the next nem_step then walks the same list), then decodes the
+ * list with the passes' own predicate:
+ *   which = 0: the neighbours the passes sum over;
+ *   which = 1: every entry of the Verlet list (a superset).
  * row_ptr has n[r]+1 entries; col has cap entries; *nnz receives the count.
- * Returns NEM_E_NOMEM (with *nnz set) when cap is too small. */
+ * cell_xy (2 n[r] int32, may be NULL) and off_xy (2 n[r] floats, may be NULL)
+ * receive, in id order, each particle's cell coordinates and FP32 offsets, the
+ * exact inputs of the predicate. Returns NEM_E_NOMEM (with *nnz set) when cap
+ * is too small, NEM_E_INVAL for which outside {0, 1}. Allocates a device
+ * buffer for the columns (hipMalloc) and synchronises the stream. */
+int nem_neighbor_list(nem_sim* s, int32_t r, int32_t which, int64_t* row_ptr, int32_t* col, int64_t cap,
+                      int64_t* nnz, int32_t* cell_xy, float* off_xy);
+
+/* nem_neighbor_list with which = 0 and no offsets. */
 int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
 
 /* FP64 reductions of replica r at the current integer time level: momentum,

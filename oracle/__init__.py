@@ -51,6 +51,10 @@ def lib():
         L.orc_neighbors.restype = C.c_int64
         L.orc_neighbors.argtypes = [C.POINTER(OrcParams), C.c_int64, dp, dp, C.c_int32, C.c_int32,
                                     C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int64]
+        L.orc_neighbors_offsets.restype = C.c_int64
+        L.orc_neighbors_offsets.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_int32, C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                            C.c_int64]
         L.orc_operators.restype = C.c_int
         L.orc_operators.argtypes = [C.POINTER(OrcParams), C.c_int64, dp, dp, dp, dp, dp, dp, dp]
         L.orc_corotation.restype = None; L.orc_corotation.argtypes = [C.c_double, dp, dp, dp]
@@ -195,6 +199,29 @@ def neighbors(params, x, y, mode: int = 0, nc: int = 0):
             continue
         if nnz < 0:
             raise RuntimeError(f"orc_neighbors failed: {nnz}")
+        return rp, col[:nnz].copy()
+
+
+def neighbors_offsets(params, nc: int, cell_xy, off_xy):
+    """CSR of the FP32 predicate on given cell coordinates (n, 2) and FP32
+    cell-relative offsets (n, 2)."""
+    cxy = np.ascontiguousarray(cell_xy, dtype=np.int32)
+    oxy = np.ascontiguousarray(off_xy, dtype=np.float32)
+    n = cxy.shape[0]
+    cap = max(64 * n, 16)
+    while True:
+        rp = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(cap, dtype=np.int32)
+        cp = make_params(params)
+        nnz = lib().orc_neighbors_offsets(C.byref(cp), n, nc, cxy.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          oxy.ctypes.data_as(C.POINTER(C.c_float)),
+                                          rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          col.ctypes.data_as(C.POINTER(C.c_int32)), cap)
+        if nnz == -2:
+            cap *= 4
+            continue
+        if nnz < 0:
+            raise RuntimeError(f"orc_neighbors_offsets failed: {nnz}")
         return rp, col[:nnz].copy()
 
 

@@ -320,26 +320,11 @@ static int build_nlist(const orc_params* p, int64_t n, const double* x, const do
  *   rx = fl32( fl32(offx_i - offx_j) + fl32(-d_x) * fl32(cs) ),
  *   r2 = fl32( fl32(rx*rx) + fl32(ry*ry) ),
  * accepted when 0 < r2 < fl32((kappa h)^2). No fused multiply-add anywhere. */
-static int64_t fp32_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,
-                              int nc, int64_t* row_ptr, int32_t* col, int64_t cap) {
-  if (nc < 3) return -1;
-  const double csd = p->L / nc;
-  const float csf = (float)csd;
+static int64_t fp32_predicate(const orc_params* p, int64_t n, int nc, const int32_t* cx, const int32_t* cy,
+                              const float* ox, const float* oy, int64_t* row_ptr, int32_t* col, int64_t cap) {
+  const float csf = (float)(p->L / nc);
   const double Rs = orc_kappa(p->kernel) * p->h;
   const float R2f = (float)(Rs * Rs);
-  int32_t* cx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-  int32_t* cy = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-  float* ox = (float*)malloc(sizeof(float) * (size_t)(n + 1));
-  float* oy = (float*)malloc(sizeof(float) * (size_t)(n + 1));
-  if (!cx || !cy || !ox || !oy) { free(cx); free(cy); free(ox); free(oy); return -3; }
-  for (int64_t i = 0; i < n; ++i) {
-    int ix = (int)floor(x[i] / csd), iy = (int)floor(y[i] / csd);
-    if (ix < 0) ix = 0; if (ix >= nc) ix = nc - 1;
-    if (iy < 0) iy = 0; if (iy >= nc) iy = nc - 1;
-    cx[i] = ix; cy[i] = iy;
-    ox[i] = (float)(x[i] - ix * csd);
-    oy[i] = (float)(y[i] - iy * csd);
-  }
   int64_t nnz = 0;
   for (int64_t i = 0; i < n; ++i) {
     row_ptr[i] = nnz;
@@ -363,8 +348,46 @@ static int64_t fp32_neighbors(const orc_params* p, int64_t n, const double* x, c
     }
   }
   row_ptr[n] = nnz;
-  free(cx); free(cy); free(ox); free(oy);
   return nnz > cap ? -2 : nnz;
+}
+
+static int64_t fp32_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,
+                              int nc, int64_t* row_ptr, int32_t* col, int64_t cap) {
+  if (nc < 3) return -1;
+  const double csd = p->L / nc;
+  int32_t* cx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t* cy = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  float* ox = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+  float* oy = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+  if (!cx || !cy || !ox || !oy) { free(cx); free(cy); free(ox); free(oy); return -3; }
+  for (int64_t i = 0; i < n; ++i) {
+    int ix = (int)floor(x[i] / csd), iy = (int)floor(y[i] / csd);
+    if (ix < 0) ix = 0; if (ix >= nc) ix = nc - 1;
+    if (iy < 0) iy = 0; if (iy >= nc) iy = nc - 1;
+    cx[i] = ix; cy[i] = iy;
+    ox[i] = (float)(x[i] - ix * csd);
+    oy[i] = (float)(y[i] - iy * csd);
+  }
+  int64_t nnz = fp32_predicate(p, n, nc, cx, cy, ox, oy, row_ptr, col, cap);
+  free(cx); free(cy); free(ox); free(oy);
+  return nnz;
+}
+
+int64_t orc_neighbors_offsets(const orc_params* p, int64_t n, int32_t nc, const int32_t* cell_xy,
+                              const float* off_xy, int64_t* row_ptr, int32_t* col, int64_t cap) {
+  if (nc < 3) return -1;
+  int32_t* cx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t* cy = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  float* ox = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+  float* oy = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+  if (!cx || !cy || !ox || !oy) { free(cx); free(cy); free(ox); free(oy); return -3; }
+  for (int64_t i = 0; i < n; ++i) {
+    cx[i] = cell_xy[2 * i]; cy[i] = cell_xy[2 * i + 1];
+    ox[i] = off_xy[2 * i]; oy[i] = off_xy[2 * i + 1];
+  }
+  int64_t nnz = fp32_predicate(p, n, nc, cx, cy, ox, oy, row_ptr, col, cap);
+  free(cx); free(cy); free(ox); free(oy);
+  return nnz;
 }
 
 int64_t orc_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,

@@ -69,6 +69,12 @@ void orc_molecular_field3(const orc_params* p, const double* Q, const double* la
 int64_t orc_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,
                       int32_t mode, int32_t nc, int64_t* row_ptr, int32_t* col, int64_t cap);
 
+/* The FP32 predicate of mode 2 on given cell coordinates cell_xy[2i + 0/1]
+ * and cell-relative FP32 offsets off_xy[2i + 0/1] (cells of side L/nc), for
+ * particles that are kept in a cell they have moved slightly out of. */
+int64_t orc_neighbors_offsets(const orc_params* p, int64_t n, int32_t nc, const int32_t* cell_xy,
+                              const float* off_xy, int64_t* row_ptr, int32_t* col, int64_t cap);
+
 /* Volume, correction tensor, corrected gradient and Laplacian of a scalar
  * field f at positions x,y (Eqs. sphSum, sphCorrectionMatrix, sph1stDerivative,
  * and the scalar corrected Laplacian). Outputs: V[n], Bt[4n] (row major),

@@ -44,7 +44,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
-            "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy")
+            "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list")
 
 
 class NemParams(C.Structure):
@@ -98,6 +98,10 @@ def lib(path: Optional[str] = None):
     L.nem_neighbors.restype = C.c_int
     L.nem_neighbors.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int64,
                                 C.POINTER(C.c_int64)]
+    L.nem_neighbor_list.restype = C.c_int
+    L.nem_neighbor_list.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_float)]
     L.nem_diagnostics.restype = C.c_int
     L.nem_diagnostics.argtypes = [vp, C.c_int32, C.POINTER(NemDiag)]
     L.nem_deposit.restype = C.c_int
@@ -244,6 +248,29 @@ def nem_neighbors(h, r, n):
             continue
         _check(h, rc, "nem_neighbors")
         return rp, col[:nnz.value].copy()
+
+
+def nem_neighbor_list(h, r, n, which=0, offsets=False):
+    """CSR (row_ptr, col) of the pairs the passes walk (which 0) or of the
+    Verlet list (which 1); with offsets, also (cell_xy (n, 2) int32,
+    off_xy (n, 2) float32), the predicate's inputs."""
+    rp = np.zeros(n + 1, dtype=np.int64)
+    nnz = C.c_int64(0)
+    cap = 64 * n
+    cxy = np.zeros((n, 2), dtype=np.int32) if offsets else None
+    oxy = np.zeros((n, 2), dtype=np.float32) if offsets else None
+    while True:
+        col = np.zeros(max(cap, 1), dtype=np.int32)
+        rc = lib().nem_neighbor_list(C.c_void_p(h), r, which, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     col.ctypes.data_as(C.POINTER(C.c_int32)), cap, C.byref(nnz),
+                                     None if cxy is None else cxy.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     None if oxy is None else oxy.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc == NEM_E_NOMEM and nnz.value > cap:
+            cap = int(nnz.value)
+            continue
+        _check(h, rc, "nem_neighbor_list")
+        out = (rp, col[:nnz.value].copy())
+        return out + (cxy, oxy) if offsets else out
 
 
 def nem_diagnostics(h, r) -> Dict[str, float]:
@@ -454,6 +481,9 @@ class Sim:
 
     def neighbors(self, r: int = 0):
         return nem_neighbors(self.h, r, self.n[r])
+
+    def neighbor_list(self, r: int = 0, which: int = 0, offsets: bool = False):
+        return nem_neighbor_list(self.h, r, self.n[r], which, offsets)
 
     def diagnostics(self, r: int = 0):
         return nem_diagnostics(self.h, r)

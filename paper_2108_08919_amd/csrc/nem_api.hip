@@ -246,7 +246,7 @@ int read_flags(nem_sim* s, unsigned* f) {
 int status_from_flags(nem_sim* s, unsigned f) {
   if (f & ERR_RANGE) { s->err = "device index outside its buffer (access skipped)"; return NEM_E_RANGE; }
   if (f & ERR_OVERFLOW) {
-    s->err = "a tile or cell holds more particles than the LDS staging capacity, or a particle has more than 64 neighbours";
+    s->err = "a tile or cell holds more particles than the LDS staging capacity, or a particle has more than 96 entries in its neighbour list";
     return NEM_E_OVERFLOW;
   }
   if (f & ERR_NUMERIC) { s->err = "non-finite value in the state"; return NEM_E_NUMERIC; }
@@ -296,11 +296,16 @@ struct Timed {
   }
 };
 
-// Enqueue one step (rebin if requested, step-begin, passes A-D) on stream st
-// for the current parity.
-int enqueue_step(nem_sim* s, hipStream_t st) {
-  const PassCfg cfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic, s->hp[0].kernel, s->hp[0].q3d,
-                    s->hp[0].integrator};
+PassCfg pass_cfg(const nem_sim* s) {
+  return PassCfg{s->T, s->LPP, s->COMP, s->hp[0].form, s->hp[0].elastic, s->hp[0].kernel, s->hp[0].q3d,
+                 s->hp[0].integrator};
+}
+
+// The start of a step on stream st: the rebin kernels (they return at once
+// unless a rebin was requested), step-begin (decides whether pass A rebuilds
+// the Verlet list) and pass A (Verlet build or walk: the list every pass walks,
+// and the volumes).
+int enqueue_prologue(nem_sim* s, hipStream_t st) {
   {
     Timed t(s, 0);
     SortArgs a = sort_args(s, s->flags + 1);
@@ -309,10 +314,21 @@ int enqueue_step(nem_sim* s, hipStream_t st) {
   }
   StepArgs a = step_args(s);
   launch_step_begin(s->flags, a.umax_nxt, s->R, st);
-  for (int pass = 1; pass <= 4; ++pass) {
+  Timed t(s, 1);
+  if (!launch_pass_a_verlet(pass_cfg(s), a, st)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
+  return NEM_OK;
+}
+
+// Enqueue one step (prologue, then passes B-D) on stream st for the current
+// parity.
+int enqueue_step(nem_sim* s, hipStream_t st) {
+  int rc = enqueue_prologue(s, st);
+  if (rc) return rc;
+  const PassCfg cfg = pass_cfg(s);
+  StepArgs a = step_args(s);
+  for (int pass = 2; pass <= 4; ++pass) {
     Timed t(s, pass);
-    const bool ok = pass == 1 ? launch_pass_a_verlet(cfg, a, st) : launch_pass(pass, cfg, a, st);
-    if (!ok) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
+    if (!launch_pass(pass, cfg, a, st)) { s->err = "unsupported kernel configuration"; return NEM_E_INVAL; }
   }
   HIPCHK(hipGetLastError());
   return NEM_OK;
@@ -616,41 +632,75 @@ int nem_sync(nem_sim* s) {
   return status_from_flags(s, f[0]);
 }
 
-int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz) {
-  if (!s || r < 0 || r >= s->R || !row_ptr || !nnz) return NEM_E_INVAL;
+int nem_neighbor_list(nem_sim* s, int32_t r, int32_t which, int64_t* row_ptr, int32_t* col, int64_t cap,
+                      int64_t* nnz, int32_t* cell_xy, float* off_xy) {
+  if (!s || r < 0 || r >= s->R || !row_ptr || !nnz || (which != 0 && which != 1)) return NEM_E_INVAL;
   if (!s->has_state[r]) return NEM_E_STATE;
   const int n = (int)s->n[r];
-  int* d_cnt = nullptr; int64_t* d_rp = nullptr; int32_t* d_col = nullptr;
-  HIPCHK(hipMalloc(&d_cnt, sizeof(int) * n));
-  HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(int) * n, s->stream));
+  // the next step's own start: rebin if requested, then the Verlet build or walk
+  const int timing = s->timing;
+  s->timing = 0;
+  int rc = enqueue_prologue(s, s->stream);
+  s->timing = timing;
+  if (rc) return rc;
+  // counts, row pointers and offsets in the staging area (9 * max n doubles)
+  char* st = (char*)s->stage;
+  int* d_cnt = (int*)st;
+  int64_t* d_rp = (int64_t*)(st + ((sizeof(int) * (size_t)n + 7) / 8) * 8);
+  int* d_cxy = (int*)(d_rp + n + 1);
+  float* d_oxy = (float*)(d_cxy + 2 * (size_t)n);
   StepArgs a = step_args(s);
-  launch_neighbors(s->T, a, s->id, r, 0, d_cnt, nullptr, nullptr, 0, s->stream);
+  const int kern = s->hp[0].kernel;
+  launch_list_export(s->T, kern, a, r, which, 0, d_cnt, nullptr, nullptr, 0, s->stream);
+  HIPCHK(hipGetLastError());
   std::vector<int> cnt(n);
   HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  {
+    // a tile over capacity skips its particles: the counts are valid only without errors
+    unsigned f[2];
+    rc = read_flags(s, f);
+    if (rc) return rc;
+    rc = status_from_flags(s, f[0]);
+    if (rc && rc != NEM_E_SINGULAR) return rc;
+    rc = NEM_OK;
+  }
   row_ptr[0] = 0;
   for (int i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
   *nnz = row_ptr[n];
-  int rc = NEM_OK;
   if (*nnz > cap || !col) {
     rc = NEM_E_NOMEM;
   } else {
-    HIPCHK(hipMalloc(&d_rp, sizeof(int64_t) * (n + 1)));
+    int32_t* d_col = nullptr;
     HIPCHK(hipMalloc(&d_col, sizeof(int32_t) * std::max<int64_t>(*nnz, 1)));
-    HIPCHK(hipMemcpyAsync(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s->stream));
-    launch_neighbors(s->T, a, s->id, r, 1, d_cnt, d_rp, d_col, *nnz, s->stream);
-    HIPCHK(hipMemcpyAsync(col, d_col, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    hipError_t e = hipMemcpyAsync(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+      launch_list_export(s->T, kern, a, r, which, 1, d_cnt, d_rp, d_col, *nnz, s->stream);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(col, d_col, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    hipFree(d_col);
+    if (e != hipSuccess) return hip_fail(s, e, "neighbour list export");
     for (int i = 0; i < n; ++i) std::sort(col + row_ptr[i], col + row_ptr[i + 1]);
   }
-  hipFree(d_cnt);
-  if (d_rp) hipFree(d_rp);
-  if (d_col) hipFree(d_col);
+  if (cell_xy || off_xy) {
+    SortArgs sa = sort_args(s, nullptr);
+    launch_export_offsets(sa, r, n, d_cxy, d_oxy, s->stream);
+    HIPCHK(hipGetLastError());
+    if (cell_xy) HIPCHK(hipMemcpyAsync(cell_xy, d_cxy, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, s->stream));
+    if (off_xy) HIPCHK(hipMemcpyAsync(off_xy, d_oxy, sizeof(float) * 2 * n, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
   if (rc) return rc;
   unsigned f[2];
   rc = read_flags(s, f);
   if (rc) return rc;
   return status_from_flags(s, f[0]);
+}
+
+int nem_neighbors(nem_sim* s, int32_t r, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz) {
+  return nem_neighbor_list(s, r, 0, row_ptr, col, cap, nnz, nullptr, nullptr);
 }
 
 int nem_diagnostics(nem_sim* s, int32_t r, nem_diag* out) {

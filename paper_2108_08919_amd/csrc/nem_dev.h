@@ -9,7 +9,7 @@ namespace nem {
 constexpr int WG = 256;          // threads per workgroup of every pair pass
 constexpr int MAXT = 8;          // largest tile side in cells
 constexpr int MAXSC = (MAXT + 2) * (MAXT + 2);  // staged cells per tile (interior + halo)
-constexpr int KMAX = 64;         // accepted neighbours per particle (list capacity)
+constexpr int KMAX = 96;         // list capacity: entries per particle of the Verlet and direct-search lists
 constexpr int UMAX_SLOTS = 64;   // per-replica slots of the max-speed reduction
 
 // Sticky device error bits (flags[0]).
@@ -79,11 +79,12 @@ struct StepArgs {
   unsigned* flags;        // [0] error bits, [1] rebin request, [2] Verlet rebuild request, [3] rebuild this step
   const unsigned* umax_cur;  // [R][UMAX_SLOTS]: max |u^{n+1/2}| (float bits)
   unsigned* umax_nxt;        // [R][UMAX_SLOTS]: max |u^{n+3/2}| being accumulated
-  uint32_t* nl;              // neighbour list: word w of particle g at nl[w*ntot + g],
-                             // two 16-bit entries (LDS slot | (dx+1)<<12 | (dy+1)<<14)
-  int* ncnt;                 // accepted neighbours per particle
+  uint32_t* nl;              // neighbour list of the direct search (diagnostics): word w of particle g
+                             // at nl[w*ntot + g], two 16-bit entries (LDS slot | (dx+1)<<12 | (dy+1)<<14)
+  int* ncnt;                 // its length per particle
   float* feat;               // NULL, or 12 features per particle at [g] (storage order)
-  uint32_t* vl;              // Verlet list (pairs within the Verlet radius), layout as nl
+  uint32_t* vl;              // Verlet list (pairs within the Verlet radius at the last build), layout as nl;
+                             // every pass walks it through the neighbour predicate
   int* vcnt;                 // Verlet list length
   float2* off_build;         // offset of each particle when the Verlet list was built
   const int* id;             // particle ids (sorted order)
@@ -117,8 +118,9 @@ struct SortArgs {
 bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s);
 bool launch_pass_a_verlet(const PassCfg& c, const StepArgs& a, hipStream_t s);
 void launch_request_relist(unsigned* flags, hipStream_t st);
-void launch_neighbors(int T, const StepArgs& a, const int* sid, int rep, int mode, int* cnt,
-                      const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s);
+void launch_list_export(int T, int kern, const StepArgs& a, int rep, int which, int mode, int* cnt,
+                        const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s);
+void launch_export_offsets(const SortArgs& s, int r, int n, int* cxy, float* oxy, hipStream_t st);
 void launch_ingest(const SortArgs& s, int r, const double* in, int n, unsigned* umax, hipStream_t st);
 void launch_rebin_key(const SortArgs& s, hipStream_t st);
 void launch_sort_tail(const SortArgs& s, int k0, int n, int c0, int nc, int base, hipStream_t st);

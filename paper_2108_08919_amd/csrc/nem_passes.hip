@@ -7,16 +7,18 @@
 // number of cell sides, so pair vectors keep the precision of the offsets
 // anywhere in the box.
 //
-// Pass A tests the ~144 candidates of the 3 x 3 cell stencil once per step and
-// keeps, per particle, the accepted neighbours as 16-bit entries (LDS slot of
-// the neighbour in the tile's staging order + stencil direction). Passes B, C
-// and D stage the same tile in the same order and walk that list, so they do
-// no candidate rejection. Several lanes may share a particle (each takes every
-// lpp-th neighbour; sums are combined with wave shuffles); a tile's short tail
-// of particles is spread over more lanes.
+// Every pass walks the particle's Verlet list: the pairs of the 3 x 3 cell
+// stencil closer than 3h + delta when the list was built, as 16-bit entries
+// (LDS slot of the neighbour in the tile's staging order + stencil direction).
+// Each pass stages the same tile in the same order and puts every entry
+// through the same FP32 predicate (0 < r^2 < (3h)^2), so all four passes sum
+// over exactly the same neighbour set. Several lanes may share a particle
+// (each takes every lpp-th entry; sums are combined with wave shuffles); a
+// tile's short tail of particles is spread over more lanes.
 //
-//   pass A  neighbour list; volume V_i = 1 / sum_j W_ij (Eq. sphSum, self
-//           included)
+//   pass A  Verlet list (rebuilt from the ~144 candidates of the stencil when
+//           particles have moved too far); volume V_i = 1 / sum_j W_ij
+//           (Eq. sphSum, self included)
 //   pass B  correction tensor and B = alpha^{-1} (Eq. sphCorrectionMatrix),
 //           velocity gradient and continuity (Eqs. sph1stDerivative,
 //           sphContinuity), Q gradient and Laplacian, molecular field
@@ -47,29 +49,28 @@ __device__ __forceinline__ float wave_sum(float v, int lpp) {
   for (int o = 1; o < lpp; o <<= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ __forceinline__ int wave_sum_int(int v, int lpp) {
+  for (int o = 1; o < lpp; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
 
-// Pair geometry of a listed neighbour: same operations as the predicate, so the
-// vector and r^2 are bit-identical to those pass A accepted.
-__device__ __forceinline__ void listed_pair(uint32_t e, const float2* shift, int jmax, const float2* s_off,
-                                            float2 oi, int& j, float& rx, float& ry, float& r2) {
+// Pair geometry of a list entry (LDS slot | direction code << 12) through the
+// neighbour predicate: true when the pair is a neighbour at this step's
+// positions. Every pass, and the list export, decides with this one function.
+__device__ __forceinline__ bool verlet_pair(uint32_t e, const float2* shift, int jmax, const float2* s_off,
+                                            float2 oi, float R2, int& j, float& rx, float& ry, float& r2) {
   j = min((int)(e & 0xFFFu), jmax);
   const float2 sh = shift[(e >> 12) & 15u];
   const float2 oj = s_off[j];
-  pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, 3.4e38f, rx, ry, r2);
+  return pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R2, rx, ry, r2);
 }
 
 // The 32-bit words of one particle's list (two 16-bit entries each, rows
 // `stride` words apart), each loaded two words before it is used. The register
 // copy w0 = w1 makes the compiler wait for a load at the top of the next
 // iteration, so one iteration's pair work overlaps each load's latency (a
-// load waited for at once left the passes stalled on HBM).
-// CLAMP 0: rows past the particle's nw words are not loaded. CLAMP 1: every
-// load is issued (the same for every lane, so the compiler can wait for it a
-// whole iteration later even where the walk also stores): a row past the
-// particle's words is clamped to its last word's row (row 0 when the list is
-// empty; KMAX/2 rows are allocated for every particle), a cached re-read whose
-// word is never used.
-template <int CLAMP>
+// load waited for at once left the passes stalled on HBM). Rows past the
+// particle's nw words are not loaded.
 struct ListStream {
   const uint32_t* p;
   size_t stride;
@@ -77,26 +78,20 @@ struct ListStream {
   uint32_t w0, w1;
   __device__ __forceinline__ ListStream(const uint32_t* p_, size_t stride_, int nwords)
       : p(p_), stride(stride_), nw(nwords), m(2) {
-    if (CLAMP) {
-      w0 = p[0];
-      w1 = p[(size_t)min(1, max(nw - 1, 0)) * stride];
-    } else {
-      w0 = nw > 0 ? p[0] : 0u;
-      w1 = nw > 1 ? p[stride] : 0u;
-    }
+    w0 = nw > 0 ? p[0] : 0u;
+    w1 = nw > 1 ? p[stride] : 0u;
   }
   __device__ __forceinline__ uint32_t next() {
     const uint32_t w = w0;
     w0 = w1;
-    if (CLAMP) w1 = p[(size_t)min(m, max(nw - 1, 0)) * stride];
-    else w1 = m < nw ? p[(size_t)m * stride] : 0u;
+    w1 = m < nw ? p[(size_t)m * stride] : 0u;
     ++m;
     return w;
   }
 };
 
-// Walk the neighbour list of particle g: lane `sub` of `lpp` takes entries
-// sub, sub+lpp, ...; flush() closes a compensation chunk every 16 pairs (the
+// Walk the list of particle g: lane `sub` of `lpp` takes entries sub,
+// sub+lpp, ...; flush() closes a compensation chunk every 16 entries (the
 // last, open chunk is summed by the accumulators' value()).
 // WPI: list words per iteration of the one-lane walk (2 puts four pairs of
 // work behind each load; the chunking of the compensated sums is the same).
@@ -105,7 +100,7 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
                                             int sub, Body&& body, Flush&& flush) {
   const uint32_t* p = nl + g;
   if (lpp == 1) {
-    ListStream<0> ls(p, (size_t)ntot, (cnt + 1) >> 1);
+    ListStream ls(p, (size_t)ntot, (cnt + 1) >> 1);
     int k = 0;
     if constexpr (WPI == 2) {
       for (; k + 3 < cnt; k += 4) {
@@ -135,7 +130,10 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
   }
 }
 
-// ------------------------------------------------------------------ pass A
+// --------------------------------------------- direct search (diagnostics)
+// Volumes and an explicit neighbour list (nl, ncnt) at given offsets, for the
+// free-energy kernel of the diagnostics, which runs between steps on the
+// integer-level positions. The step itself uses the Verlet list below.
 // Phase 1 runs the predicate over the candidates of the nine stencil cells and
 // records, per cell, one 64-bit word: the accepted particles as a mask in bits
 // 0-47 (bit b = b-th particle of the cell; a cell holds at most 48), the
@@ -230,69 +228,24 @@ __device__ __forceinline__ void tile_pass_a(const StepArgs& a, int w) {
 }
 
 // ------------------------------------------------------------- pass A, Verlet
-// Between builds of the Verlet list (every pair of the 3 x 3 stencil closer
-// than 3h + delta, delta = 0.075 h), pass A walks that list instead of the ~144
-// candidates: each listed pair is put through the exact predicate again and the
-// accepted ones make the step's neighbour list, sums and counts, exactly as
-// the candidate search would. The list stays a superset while no particle has
-// moved more than 0.45 delta since the build (pass D checks and requests a
-// rebuild, as does every rebin, new state, tile change or snapshot restore):
-// a pair left out was at least 3h + delta apart, so it is still more than
-// 3h + 0.1 delta apart; pairs outside the stencil are excluded by the rebin
-// criterion as before.
+// The Verlet list holds every pair of the 3 x 3 stencil closer than 3h + delta
+// (delta = 0.075 h) at the last build. It stays a superset of the neighbour
+// set while no particle has moved more than 0.45 delta since the build (pass D
+// checks and requests a rebuild, as does every rebin, new state, tile change
+// or snapshot restore): a pair left out was at least 3h + delta apart, so it is
+// still more than 3h + 0.1 delta apart; pairs outside the stencil are excluded
+// by the rebin criterion. Every pass walks it and applies the exact predicate,
+// so the candidate search of the ~144 stencil particles runs only on rebuild
+// steps. Pass A sums the kernel over the accepted pairs (the volume).
 
-// The step's neighbour list of one particle under construction: accepted pairs
-// are summed (V) and appended as 16-bit entries. Entries go
-// through a ring of RING words in this lane's column of an LDS buffer (word m
-// at lw[(m % RING) * WG]) that is copied to the list every 2 RING entries and
-// at the end, so that the walk issues its global stores in bursts: they share
-// the load counter with the list words the walk loads ahead.
-constexpr int RING = 8;
-template <int COMP, int KERN>
-struct ExactSink {
-  Acc<COMP> sw;
-  int kept;
-  uint32_t word;
-  uint32_t* lw;
-  uint32_t* dst;
-  size_t ntot;
-  __device__ __forceinline__ void init(uint32_t* lds_column, const StepArgs& a, int g) {
-    sw.init();
-    kept = 0; word = 0u; lw = lds_column; dst = a.nl + g; ntot = (size_t)a.ntot;
-  }
-  __device__ __forceinline__ void take(const RepDev& R, uint32_t e, float rx, float ry, float r2) {
-    sw.add(kernel_raw<KERN>(R, r2).W);
-    if (kept < KMAX) {
-      if (kept & 1) lw[((kept >> 1) % RING) * WG] = word | (e << 16);
-      else word = e;
-    }
-    ++kept;
-    if ((kept & 15) == 0) sw.end_cell();
-    if ((kept & (2 * RING - 1)) == 0 && kept <= KMAX) {
-      const int m0 = (kept >> 1) - RING;
-#pragma unroll
-      for (int i = 0; i < RING; ++i) dst[(size_t)(m0 + i) * ntot] = lw[i * WG];
-    }
-  }
-  __device__ __forceinline__ void finish(const StepArgs& a, const RepDev& R, int g) {
-    const int nk = min(kept, KMAX);
-    if (nk & 1) lw[((nk >> 1) % RING) * WG] = word;
-    for (int m = (nk >> 1) / RING * RING; m < (nk + 1) >> 1; ++m) dst[(size_t)m * ntot] = lw[(m % RING) * WG];
-    if (kept > KMAX) flag(a.flags, ERR_OVERFLOW);
-    a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
-    a.ncnt[g] = nk;
-  }
-};
-
-// Build: candidate search with the Verlet radius (masks as in pass A), then one
-// walk over the Verlet pairs in cell order that writes the Verlet list and
-// feeds the pairs passing the exact predicate to the step's list.
+// Build: candidate search with the Verlet radius (masks as in the direct
+// search), then one walk over the Verlet pairs in cell order that writes the
+// list and sums W over the pairs that pass the exact predicate.
 template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
   __shared__ unsigned long long s_mask[9 * WG];
-  __shared__ uint32_t s_outw[RING * WG];   // step-list ring, lane-minor
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -339,8 +292,8 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     if (cnt > KMAX || big) flag(a.flags, ERR_OVERFLOW);
-    ExactSink<COMP, KERN> out;
-    out.init(s_outw + threadIdx.x, a, g);
+    Acc<COMP> sw;
+    sw.init();
     int c = -1;
     unsigned long long m = 0ull, x = 0ull;
     uint32_t vword = 0u;
@@ -357,24 +310,23 @@ __device__ __forceinline__ void tile_pass_a_build(const StepArgs& a, int w) {
       const uint32_t e = (uint32_t)j | (hi & 0xF000u);
       if (k & 1) vdst[(size_t)(k >> 1) * a.ntot] = vword | (e << 16);
       else vword = e;
-      const float2 sh = L.shift[hi >> 12];
-      const float2 oj = s_off[j];
+      int jj;
       float rx, ry, r2;
-      if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) out.take(R, e, rx, ry, r2);
+      if (verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, jj, rx, ry, r2)) sw.add(kernel_raw<KERN>(R, r2).W);
+      if ((k & 15) == 15) sw.end_cell();
     }
     if (vk & 1) vdst[(size_t)(vk >> 1) * a.ntot] = vword;
     a.vcnt[g] = vk;
     a.off_build[g] = oi;
-    out.finish(a, R, g);
+    a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
   }
 }
 
-// Walk: the Verlet pairs of each particle through the exact predicate.
+// Walk: the volume over the Verlet entries that pass the exact predicate.
 template <int T, int COMP, int KERN>
 __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
   __shared__ TileLDS<T> L;
   __shared__ float2 s_off[TileCfg<T, KERN>::MAXP];
-  __shared__ uint32_t s_outw[RING * WG];   // step-list ring, lane-minor
   RepDev R;
   int rep;
   if (!tile_begin<T, KERN>(a, w, L, R, rep)) return;
@@ -390,26 +342,15 @@ __device__ __forceinline__ void tile_pass_a_walk(const StepArgs& a, int w) {
     const int g = L.gstart[st] + (p - L.cstart[st]);
     if (g < 0 || g >= a.ntot) { flag(a.flags, ERR_RANGE); continue; }
     const float2 oi = s_off[p];
-    const int vk = min(a.vcnt[g], KMAX);
-    ExactSink<COMP, KERN> out;
-    out.init(s_outw + threadIdx.x, a, g);
-    ListStream<1> ls(a.vl + g, (size_t)a.ntot, (vk + 1) >> 1);
-    for (int k = 0; k < vk; k += 4) {   // two words per iteration: more work behind each load
-      const uint32_t wa = ls.next();
-      const uint32_t wb = ls.next();
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        if (k + h >= vk) break;
-        const uint32_t wd = h < 2 ? wa : wb;
-        const uint32_t e = (h & 1) ? (wd >> 16) : (wd & 0xFFFFu);
-        const int j = min((int)(e & 0xFFFu), S - 1);
-        const float2 sh = L.shift[(e >> 12) & 15u];
-        const float2 oj = s_off[j];
-        float rx, ry, r2;
-        if (pair_accept(oi.x, oi.y, oj.x, oj.y, sh.x, sh.y, R.R2, rx, ry, r2)) out.take(R, e, rx, ry, r2);
-      }
-    }
-    out.finish(a, R, g);
+    Acc<COMP> sw;
+    sw.init();
+    each_listed<2>(a.vl, a.ntot, g, min(a.vcnt[g], KMAX), 1, 0, [&](uint32_t e) {
+      int j; float rx, ry, r2;
+      const bool in = verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2);
+      const float W = kernel_raw<KERN>(R, r2).W;
+      sw.add(in ? W : 0.0f);                 // exact zero outside the support
+    }, [&]() { sw.end_cell(); });
+    a.V[g] = 1.0f / (R.a2 * (kernel_w0_raw<KERN>() + sw.value()));
   }
 }
 
@@ -477,10 +418,12 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       if constexpr (Q3 == 1) qci = s_qc[p];
       if constexpr (FORM == 1) ri = s_rho[p];
       const float ri2inv = 1.0f / (ri * ri);
-      const int cnt = min(a.ncnt[g], KMAX);
-      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      const int cnt = min(a.vcnt[g], KMAX);
+      each_listed(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
+        // entries outside the support are skipped (a branch measured faster
+        // here than zeroing their terms with selects)
+        if (!verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2)) return;
         const KW k = kernel_raw<KERN>(R, r2);
         const float2 uj = s_u[j], qj = s_q[j];
         const float c = s_V[j] * k.F;          // V_j W'(r)/r
@@ -681,11 +624,15 @@ __device__ __forceinline__ void tile_pass_c(const StepArgs& a, int w) {
     sd.init(); Wux.init(); Wuy.init();
     if (act) {
       const float2 oi = s_off[p], ui = s_u[p];
-      const int cnt = min(a.ncnt[g], KMAX);
-      each_listed<2>(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      const int cnt = min(a.vcnt[g], KMAX);
+      each_listed<2>(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
-        const float W = kernel_raw<KERN>(R, r2).W;
+        // entries outside the support add exact zeros (a select: a branch here
+        // splits the four-entry iteration and measured 9% slower); the select
+        // also drops the non-finite W of coincident particles
+        const bool in = verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2);
+        const float Wr = kernel_raw<KERN>(R, r2).W;
+        const float W = in ? Wr : 0.0f;
         const float2 uj = s_u[j];
         sd.fma(s_dh[j], W);
         Wux.fma(ui.x - uj.x, W); Wuy.fma(ui.y - uj.y, W);   // sum_j (u_i - u_j) W_ij
@@ -761,16 +708,17 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
     Px.init(); Py.init(); Exx.init(); Exy.init(); Eyx.init(); Eyy.init();
     Gx.init(); Gy.init(); Gr.init();
     float2 oi = {0.f, 0.f};
-    int cnt = 0;
+    int nacc = 0;   // accepted neighbours taken by this lane
     if (act) {
       oi = s_off[p];
       const float Pi = PV ? a.P[g] : s_P[p];
       float2 pii = {0.f, 0.f};
       if constexpr (EL == 1) pii = s_pi[p];
-      cnt = min(a.ncnt[g], KMAX);
-      each_listed(a.nl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      const int cnt = min(a.vcnt[g], KMAX);
+      each_listed(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
-        listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
+        if (!verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2)) return;   // as in pass B
+        ++nacc;
         const KW k = kernel_raw<KERN>(R, r2);
         const float c = (FORM == 0) ? s_V[j] * k.F : R.dWc * k.F;
         const float f = PV ? fmaf(Pi, s_V[j], s_P[j]) * k.F : (Pi + s_P[j]) * c;
@@ -790,6 +738,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
     }
     const float prx = wave_sum(Px.value(), lpp), pry = wave_sum(Py.value(), lpp);
     const float gx = wave_sum(Gx.value(), lpp), gy = wave_sum(Gy.value(), lpp), gr = wave_sum(Gr.value(), lpp);
+    const int cnt = wave_sum_int(nacc, lpp);
     float exx = 0.f, exy = 0.f, eyx = 0.f, eyy = 0.f;
     if constexpr (EL == 1) {
       exx = wave_sum(Exx.value(), lpp); exy = wave_sum(Exy.value(), lpp);
@@ -886,7 +835,8 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
 // Laplacian (F) and through squared corrected gradients (F_grad):
 //   F_i    = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 - K/2 Q:lapQ]
 //   F_grad = V_i [A/2 trQ^2 + C/4 (trQ^2)^2 + K/2 sum_abc (d_c Q_ab)^2]
-// (trQ^3 = 0 in 2D). Runs after pass A on the integer-level offsets.
+// (trQ^3 = 0 in 2D). Runs after the direct search on the integer-level offsets
+// and walks its list (every entry passes the predicate again, as in the passes).
 template <int T, int KERN>
 __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe) {
   __shared__ TileLDS<T> L;
@@ -922,7 +872,7 @@ __global__ __launch_bounds__(WG) void k_free_energy(const StepArgs a, double* fe
     const float qci = R.q3d ? s_qc[p] : 0.0f;
     each_listed(a.nl, a.ntot, g, min(a.ncnt[g], KMAX), 1, 0, [&](uint32_t e) {
       int j; float rx, ry, r2;
-      listed_pair(e, L.shift, S - 1, s_off, oi, j, rx, ry, r2);
+      if (!verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2)) return;
       const KW k = kernel_wf<KERN>(R, r2);
       const float c = s_V[j] * k.F, cx = c * rx, cy = c * ry;
       const float txx = cx * rx, txy = cx * ry, tyy = cy * ry;
@@ -992,52 +942,49 @@ void launch_free_energy(int T, int kern, const StepArgs& a, double* fe, hipStrea
 }
 
 // ---------------------------------------------------------- neighbour export
-// mode 0: count neighbours of each particle into cnt[id]; mode 1: write ids.
-template <int T>
-__global__ __launch_bounds__(WG) void k_neighbors(const StepArgs a, const int* sid, int rep_only, int mode,
-                                                  int* cnt, const int64_t* row_ptr, int32_t* col,
-                                                  int64_t cap) {
+// The pairs the pair passes sum over, decoded from the Verlet list exactly as
+// they walk it: which = 0 keeps the entries that pass the predicate
+// (verlet_pair, the passes' own decision), which = 1 every entry of the list.
+// mode 0 counts the entries of each particle of replica rep_only into
+// cnt[id]; mode 1 writes the neighbours' ids from row_ptr[id] on.
+template <int T, int KERN>
+__global__ __launch_bounds__(WG) void k_list_export(const StepArgs a, int rep_only, int which, int mode, int* cnt,
+                                                    const int64_t* row_ptr, int32_t* col, int64_t cap) {
   __shared__ TileLDS<T> L;
-  constexpr int MP = TileCfg<T>::MAXP;
+  constexpr int MP = TileCfg<T, KERN>::MAXP;
   __shared__ float2 s_off[MP];
   __shared__ int s_id[MP];
   RepDev R;
   int rep;
-  if (!tile_begin<T>(a, blockIdx.x, L, R, rep)) return;
+  if (!tile_begin<T, KERN>(a, blockIdx.x, L, R, rep)) return;
   if (rep != rep_only) return;
-  const int ni = L.hdr[0], nint = L.hdr[2], nreg = L.hdr[3];
+  const int nint = L.hdr[2], nreg = L.hdr[3];
   const int S = L.cstart[nreg];
   for (int t = threadIdx.x; t < S; t += WG) {
     const int g = staged_global<T>(a, L, t);
     s_off[t] = a.off_cur[g];
-    s_id[t] = sid[g];
+    s_id[t] = a.id[g];
   }
   __syncthreads();
   const int nin = L.cstart[nint];
   for (int p = threadIdx.x; p < nin; p += WG) {
     const int st = find_cell(L.cstart, nint, p);
-    const int li = st % ni, lj = st / ni;
-    const float2 oi = s_off[p];
+    const int g = L.gstart[st] + (p - L.cstart[st]);
     const int idi = s_id[p];
-    if (idi < 0 || idi >= R.n) { flag(a.flags, ERR_RANGE); continue; }
+    if (g < 0 || g >= a.ntot || idi < 0 || idi >= R.n) { flag(a.flags, ERR_RANGE); continue; }
+    const float2 oi = s_off[p];
     int c = 0;
-    int64_t base = (mode == 1) ? row_ptr[idi] : 0;
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int sc = L.slot[(lj + dy + 1) * (ni + 2) + (li + dx + 1)];
-        const float sx = (float)(-dx) * R.cs, sy = (float)(-dy) * R.cs;
-        for (int j = L.cstart[sc]; j < L.cstart[sc + 1]; ++j) {
-          const float2 oj = s_off[j];
-          float rx, ry, r2;
-          if (pair_accept(oi.x, oi.y, oj.x, oj.y, sx, sy, R.R2, rx, ry, r2)) {
-            if (mode == 1) {
-              if (base + c < cap) col[base + c] = s_id[j];
-              else flag(a.flags, ERR_RANGE);
-            }
-            ++c;
-          }
-        }
+    const int64_t base = (mode == 1) ? row_ptr[idi] : 0;
+    each_listed(a.vl, a.ntot, g, min(a.vcnt[g], KMAX), 1, 0, [&](uint32_t e) {
+      int j; float rx, ry, r2;
+      const bool in = verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2);
+      if (which == 0 && !in) return;
+      if (mode == 1) {
+        if (base + c < cap) col[base + c] = s_id[j];
+        else flag(a.flags, ERR_RANGE);
       }
+      ++c;
+    }, []() {});
     if (mode == 0) cnt[idi] = c;
   }
 }
@@ -1168,13 +1115,15 @@ bool launch_pass(int pass, const PassCfg& c, const StepArgs& a, hipStream_t s) {
   return false;
 }
 
-void launch_neighbors(int T, const StepArgs& a, const int* sid, int rep, int mode, int* cnt,
-                      const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s) {
+void launch_list_export(int T, int kern, const StepArgs& a, int rep, int which, int mode, int* cnt,
+                        const int64_t* row_ptr, int32_t* col, int64_t cap, hipStream_t s) {
   const dim3 grid(a.nwork), block(WG);
-  if (T == 8)
-    hipLaunchKernelGGL((k_neighbors<8>), grid, block, 0, s, a, sid, rep, mode, cnt, row_ptr, col, cap);
-  else
-    hipLaunchKernelGGL((k_neighbors<4>), grid, block, 0, s, a, sid, rep, mode, cnt, row_ptr, col, cap);
+  if (kern == 1) {
+    if (T == 8) hipLaunchKernelGGL((k_list_export<8, 1>), grid, block, 0, s, a, rep, which, mode, cnt, row_ptr, col, cap);
+    else hipLaunchKernelGGL((k_list_export<4, 1>), grid, block, 0, s, a, rep, which, mode, cnt, row_ptr, col, cap);
+  } else {
+    if (T == 8) hipLaunchKernelGGL((k_list_export<8, 0>), grid, block, 0, s, a, rep, which, mode, cnt, row_ptr, col, cap);
+    else hipLaunchKernelGGL((k_list_export<4, 0>), grid, block, 0, s, a, rep, which, mode, cnt, row_ptr, col, cap);
+  }
 }
-
 }  // namespace nem

@@ -280,6 +280,24 @@ __global__ void k_export(SortArgs s, int r, double* out, int n) {
   }
 }
 
+// Cell coordinates and FP32 offsets (high part) of every particle of replica r
+// at r^{n+1/2}, the values the neighbour predicate of the next step reads:
+// cxy[2 id + 0/1] = cell x/y, oxy[2 id + 0/1] = offset x/y from the cell corner.
+__global__ void k_export_offsets(SortArgs s, int r, int n, int* cxy, float* oxy) {
+  const RepDev R = s.reps[r];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = R.part_base + i;
+    const int id = s.id[k];
+    const int c = s.cell[k] - R.cell_base;
+    if (id < 0 || id >= n || c < 0 || c >= R.nc * R.nc) { atomicOr(s.flags, ERR_RANGE); continue; }
+    const float2 o = s.off[k];
+    cxy[2 * (size_t)id] = c % R.nc;
+    cxy[2 * (size_t)id + 1] = c / R.nc;
+    oxy[2 * (size_t)id] = o.x;
+    oxy[2 * (size_t)id + 1] = o.y;
+  }
+}
+
 // Qyy of replica r (quasi-2D variant) to or from an FP64 array in id order:
 // to_device != 0 copies buf[id] into the sorted array, else the reverse.
 __global__ void k_qyy_io(SortArgs s, int r, int n, double* buf, int to_device) {
@@ -437,6 +455,10 @@ void launch_reduce(const SortArgs& s, int r, int n, const double* fe, double* re
 }
 void launch_export(const SortArgs& s, int r, double* out, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_export, dim3(grid_for(n)), dim3(256), 0, st, s, r, out, n);
+}
+
+void launch_export_offsets(const SortArgs& s, int r, int n, int* cxy, float* oxy, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_offsets, dim3(grid_for(n)), dim3(256), 0, st, s, r, n, cxy, oxy);
 }
 
 void launch_qyy_io(const SortArgs& s, int r, int n, double* buf, int to_device, hipStream_t st) {

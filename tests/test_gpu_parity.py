@@ -67,6 +67,67 @@ def test_neighbors_bit_exact(kind, L, seed):
     sim.close()
 
 
+def _walked_list_matches_oracle(sim, p, L):
+    """The walked list (what passes A-D sum over) against the oracle's FP32
+    predicate on the GPU's own cells and offsets: identical sets."""
+    rp, col, cxy, oxy = sim.neighbor_list(0, 0, offsets=True)
+    sim.check()
+    nc = int(np.floor(L / (oracle.kappa(p.kernel) * p.h + p.skin)))
+    orp, ocol = oracle.neighbors_offsets(p, nc, cxy, oxy)
+    assert csr_rows(rp, col) == csr_rows(orp, ocol)
+    return rp, col
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_walked_list_many_steps_after_build(kernel):
+    """A drifting jittered state: the Verlet list built at step 1 is walked for
+    50 steps (it is the same list before and after), the neighbour set changes
+    under it (pairs cross the support radius), and at every stage the pairs
+    the passes walk are exactly the oracle's neighbour set."""
+    import paper_2108_08919_amd as P
+    L = 40
+    p = wl.Params(L=float(L), zeta=0.03, kernel=kernel)
+    s0 = random_state(L, 3, amp_u=0.1)
+    say("walked list", kernel)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    sim.step(1)
+    v1 = csr_rows(*sim.neighbor_list(0, 1))        # Verlet list in use at step 2
+    n1 = csr_rows(*_walked_list_matches_oracle(sim, p, L))
+    sim.step(50)
+    v2 = csr_rows(*sim.neighbor_list(0, 1))
+    n2 = csr_rows(*_walked_list_matches_oracle(sim, p, L))
+    assert v1 == v2                                  # no rebuild: the list was walked
+    changed = sum(a != b for a, b in zip(n1, n2))
+    say("rows whose neighbour set changed while walking:", changed)
+    assert changed > 10
+    # the walked set is a strict subset of the Verlet list, row by row
+    assert all(set(a) <= set(b) for a, b in zip(n2, v2))
+    assert sum(len(b) - len(a) for a, b in zip(n2, v2)) > 0
+    sim.close()
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_walked_list_after_rebuilds_and_rebin(kernel):
+    """A uniform drift of 0.007 per step rebuilds the Verlet list every few
+    steps and rebins after about 35: particles then sit in cells they have
+    partly left, and the walked list still equals the oracle's predicate on
+    the GPU's own offsets."""
+    import paper_2108_08919_amd as P
+    L = 32
+    p = wl.Params(L=float(L), zeta=0.02, kernel=kernel)
+    s0 = random_state(L, 8, amp_u=0.05)
+    s0["ux"] = s0["ux"] + 7.0
+    s0["uy"] = s0["uy"] - 5.0
+    say("walked list after rebuilds", kernel)
+    sim = P.Sim([p], [L * L])
+    sim.set_state(0, s0)
+    for _ in range(4):
+        sim.step(11)
+        _walked_list_matches_oracle(sim, p, L)
+    sim.close()
+
+
 # --------------------------------------------------------------- state I/O
 
 def test_state_roundtrip():
