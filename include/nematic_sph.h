@@ -213,6 +213,21 @@ int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_mi
 int nem_vorticity_correlation(nem_sim* s, int32_t r, int32_t M, double* c_x, double* c_y, double* l_x,
                               double* l_y);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * nem_defects without its first-use grid allocation. The same kernels write
+ * the M x M deposit grid and the two counters into a static device array of
+ * the library, 8 MiB + 256 bytes per GPU, held from the library's load until
+ * the process ends (its address is looked up once per device by nem_create).
+ * M must be a power of two in [8, NEM_NOALLOC_MAX_GRID]; larger grids return
+ * NEM_E_INVAL with an explanation in nem_last_error. The call allocates
+ * nothing (no hipMalloc, no hipFree); the counters are cleared by a kernel on
+ * every call. All calls on one GPU share the array: calls that overlap on one
+ * GPU (several threads, or several streams in flight) race and must be
+ * serialised by the caller. Synchronises the stream, like nem_defects. */
+#define NEM_NOALLOC_MAX_GRID 512
+int nem_defects_noalloc(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus);
+
 /* Lagrangian diagnostics (paper Sec. 5: pathlines of tagged particles, mixing
  * of colour-marked regions).
  *

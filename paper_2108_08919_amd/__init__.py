@@ -44,7 +44,8 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_nparams", "nem_mlp_create", "nem_mlp_set_weights", "nem_mlp_get_weights", "nem_mlp_set_norm",
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
-            "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list")
+            "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list",
+            "nem_defects_noalloc")
 
 
 class NemParams(C.Structure):
@@ -110,6 +111,8 @@ def lib(path: Optional[str] = None):
     L.nem_spectrum.argtypes = [vp, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, C.c_int32, dp]
     L.nem_defects.restype = C.c_int
     L.nem_defects.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.nem_defects_noalloc.restype = C.c_int
+    L.nem_defects_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.nem_vorticity_correlation.restype = C.c_int
     L.nem_vorticity_correlation.argtypes = [vp, C.c_int32, C.c_int32, dp, dp, dp, dp]
     L.nem_set_qyy.restype = C.c_int
@@ -296,6 +299,12 @@ def nem_spectrum(h, r, M, k_lo: int = 0, k_hi: int = 0):
 def nem_defects(h, r, M):
     a, b = C.c_int64(0), C.c_int64(0)
     _check(h, lib().nem_defects(C.c_void_p(h), r, M, C.byref(a), C.byref(b)), "nem_defects")
+    return a.value, b.value
+
+
+def nem_defects_noalloc(h, r, M):
+    a, b = C.c_int64(0), C.c_int64(0)
+    _check(h, lib().nem_defects_noalloc(C.c_void_p(h), r, M, C.byref(a), C.byref(b)), "nem_defects_noalloc")
     return a.value, b.value
 
 
@@ -496,6 +505,10 @@ class Sim:
 
     def defects(self, r: int = 0, M: int = 0):
         return nem_defects(self.h, r, M or int(self.params[r].L))
+
+    def defects_noalloc(self, r: int = 0, M: int = 0):
+        """nem_defects on the library's static scratch (no allocation; M <= 512)."""
+        return nem_defects_noalloc(self.h, r, M or int(self.params[r].L))
 
     def vorticity_correlation(self, r: int = 0, M: int = 0):
         """(C_x, C_y, l_x, l_y): vorticity autocorrelation along x and y on the

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,9 +24,42 @@ using namespace nem;
 using namespace nem_host;
 
 
+// Scratch of the entry points that allocate nothing (nem_defects_noalloc): the
+// M x M deposit grid (4 fields, FP64) for M <= NEM_NOALLOC_MAX_GRID, then two
+// 64-bit defect counters. One copy per GPU for the life of the process; every
+// call on a GPU shares it, so calls that overlap on one GPU race.
+constexpr size_t NOALLOC_GRID_BYTES = sizeof(double) * 4 * (size_t)NEM_NOALLOC_MAX_GRID * NEM_NOALLOC_MAX_GRID;
+constexpr size_t NOALLOC_BYTES = NOALLOC_GRID_BYTES + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Clears n 64-bit counters (a kernel, so that the call holds no memset node if
+// a caller captures it).
+__global__ void k_clear_u64(unsigned long long* p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0ull;
+}
+
 namespace nem_host {
 
 constexpr size_t ALIGN = 256;
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+// Returns nullptr when the lookup fails.
+void* scratch_address(int dev, hipError_t* err) {
+  static std::mutex mu;
+  static void* addr[256] = {nullptr};
+  std::lock_guard<std::mutex> lock(mu);
+  *err = hipSuccess;
+  if (dev < 0 || dev >= 256) { *err = hipErrorInvalidDevice; return nullptr; }
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) { *err = e; return nullptr; }
+    addr[dev] = ptr;
+  }
+  return addr[dev];
+}
 
 struct Layout {
   size_t total = 0;
@@ -528,6 +562,10 @@ int nem_create(const nem_params* p, const int64_t* n, int32_t R, void* dev_arena
   }
   s->has_state.assign(R, 0);
   hipError_t e = hipSuccess;
+  // the no-allocation entry points' scratch on the current device
+  e = hipGetDevice(&s->device);
+  if (e == hipSuccess) s->scratch = scratch_address(s->device, &e);
+  if (e != hipSuccess) { hip_fail(s, e, "scratch lookup (hipGetSymbolAddress)"); nem_destroy(s); return NEM_E_HIP; }
   // zero the whole arena once: counts and cursors must start at zero, and
   // replicas without a state keep empty cells
   if (e == hipSuccess) e = hipMemsetAsync(b, 0, o.total - ALIGN, s->stream);
@@ -914,6 +952,39 @@ int nem_defects(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_mi
   *n_minus = (int64_t)c[1];
   unsigned f[2];
   rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_defects_noalloc(nem_sim* s, int32_t r, int32_t M, int64_t* n_plus, int64_t* n_minus) {
+  if (!s || !n_plus || !n_minus) return NEM_E_INVAL;
+  if (r < 0 || r >= s->R) { s->err = "replica index out of range"; return NEM_E_INVAL; }
+  if (M < 8 || M > NEM_NOALLOC_MAX_GRID || (M & (M - 1))) {
+    s->err = "nem_defects_noalloc: grid side must be a power of two in [8, " + std::to_string(NEM_NOALLOC_MAX_GRID) +
+             "] (the size of its static scratch)";
+    return NEM_E_INVAL;
+  }
+  if (!s->has_state[r]) { s->err = "state of this replica was never set"; return NEM_E_STATE; }
+  if (!s->scratch) { s->err = "no scratch on this device"; return NEM_E_HIP; }
+  double* grid = (double*)s->scratch;
+  unsigned long long* cnt = (unsigned long long*)((char*)s->scratch + NOALLOC_GRID_BYTES);
+  // the same kernels as nem_defects: integer-level offsets (arena), deposit
+  // (writes every node of the M x M grid), counters cleared, winding
+  SortArgs a = sort_args(s, nullptr);
+  launch_int_offsets(a, s->t_off, s->stream);
+  StepArgs sa = step_args(s);
+  sa.off_cur = s->t_off;
+  launch_deposit(s->T, s->hp[r].kernel, sa, r, M, grid, s->stream);
+  hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, s->stream, cnt, 2);
+  launch_winding(grid, M, cnt, s->stream);
+  HIPCHK(hipGetLastError());
+  unsigned long long c[2];
+  HIPCHK(hipMemcpyAsync(c, cnt, sizeof(c), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *n_plus = (int64_t)c[0];
+  *n_minus = (int64_t)c[1];
+  unsigned f[2];
+  int rc = read_flags(s, f);
   if (rc) return rc;
   return status_from_flags(s, f[0]);
 }

@@ -72,6 +72,8 @@ struct nem_sim {
     int parity = 0;
     std::vector<float> dt;
   } snap[2];  // two, so that a learned macro step can run while the previous one is checked
+  int device = 0;            // device current at nem_create
+  void* scratch = nullptr;   // that device's copy of the no-allocation scratch
   std::string err;
 };
 
