@@ -15,11 +15,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
 
 
-def field_errors(g, o, s0, L):
+def field_errors(g, o, s0, L, nsteps=None):
     """Per-field relative L2 errors of GPU fields g against oracle fields o
     (both dicts in id order). Position errors are measured on displacements
-    from the start state s0 and on the absolute positions."""
+    from the start state s0 and on the absolute positions. With nsteps, the
+    increment errors of increment_errors() are included as well."""
     e = {}
+    if nsteps:
+        e.update(increment_errors(g, o, s0, L, nsteps))
     dgx, dgy = minimg(g["x"] - s0["x"], L), minimg(g["y"] - s0["y"], L)
     dox, doy = minimg(o["x"] - s0["x"], L), minimg(o["y"] - s0["y"], L)
     ex, ey = minimg(g["x"] - o["x"], L), minimg(g["y"] - o["y"], L)
@@ -36,6 +39,63 @@ def field_errors(g, o, s0, L):
     e["drho"] = rel_l2(g["rho"] - s0["rho"], o["rho"] - s0["rho"])
     e["a"] = rel_l2(np.concatenate([g["ax"], g["ay"]]), np.concatenate([o["ax"], o["ay"]]))
     return e
+
+
+EPS32 = 2.0 ** -24   # unit roundoff of FP32 storage
+
+
+def increment_errors(g, o, s0, L, nsteps):
+    """Errors of the increments over a run, per field f in r, u, Q, rho (GPU g
+    and oracle o against the common start s0, all in id order):
+      d{f}_l2   ||df_g - df_o||_2 / ||df_o||_2 with df = f - f0 (minimum image
+                for r), the relative L2 error of what the steps changed;
+      d{f}_max  max_i |df_g - df_o|_i / max_i |df_o|_i, the largest element
+                error relative to the largest increment;
+      d{f}_res  max_i |df_g - df_o|_i / (nsteps * 2^-24 * max|f|), the same error
+                in units of the FP32 resolution of the stored field per step
+                (f: u and Q as stored; rho as rho - rho0, its stored form)."""
+    def pair(a, b):
+        return np.concatenate(a), np.concatenate(b)
+    fields = {
+        "r": pair([minimg(g["x"] - s0["x"], L), minimg(g["y"] - s0["y"], L)],
+                  [minimg(o["x"] - s0["x"], L), minimg(o["y"] - s0["y"], L)]),
+        "u": pair([g["ux"] - s0["ux"], g["uy"] - s0["uy"]], [o["ux"] - s0["ux"], o["uy"] - s0["uy"]]),
+        "Q": pair([g["qxx"] - s0["qxx"], g["qxy"] - s0["qxy"]], [o["qxx"] - s0["qxx"], o["qxy"] - s0["qxy"]]),
+        "rho": (g["rho"] - s0["rho"], o["rho"] - s0["rho"]),
+    }
+    scale = {
+        "r": None,
+        "u": max(np.abs(o["ux"]).max(), np.abs(o["uy"]).max()),
+        "Q": max(np.abs(o["qxx"]).max(), np.abs(o["qxy"]).max()),
+        "rho": np.abs(o["rho"] - 1.0).max(),
+    }
+    e = {}
+    for f, (dg, do) in fields.items():
+        err = np.abs(dg - do)
+        e[f"d{f}_l2"] = float(np.linalg.norm(dg - do) / max(np.linalg.norm(do), 1e-300))
+        e[f"d{f}_max"] = float(err.max() / max(np.abs(do).max(), 1e-300))
+        if scale[f] is not None:
+            e[f"d{f}_res"] = float(err.max() / (nsteps * EPS32 * max(scale[f], 1e-300)))
+    return e
+
+
+# Bars on the increments of an n-step run (the DESIGN parity section derives them):
+# * u and Q are stored in FP32, so every step rounds them once: an element of
+#   the increment can be off by about n * 2^-24 * max|f| before any arithmetic
+#   error; held to RES_BAR times that;
+# * rho is stored as rho - rho0 and its increment comes from the continuity
+#   rate's FP32 pair sums: relative L2 and largest-element error <= DRHO_BAR;
+# * positions are compensated (hi + lo) FP32 offsets: displacement errors
+#   relative to the displacements <= DR_BAR.
+RES_BAR = 4.0
+DRHO_BAR = 3e-5
+DR_BAR = 1e-5
+
+
+def check_increments(e, dr_bar=DR_BAR):
+    for k, bar in (("du_res", RES_BAR), ("dQ_res", RES_BAR), ("drho_l2", DRHO_BAR), ("drho_max", DRHO_BAR),
+                   ("dr_l2", dr_bar), ("dr_max", dr_bar)):
+        assert e[k] <= bar, (k, e[k], bar)
 
 
 def run_oracle(params, s0, nsteps, search=0):

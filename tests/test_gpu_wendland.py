@@ -11,7 +11,7 @@ import oracle
 import workloads as wl
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import field_errors, gpu_run, random_state, run_oracle  # noqa: E402
+from gpu_common import check_increments, field_errors, gpu_run, random_state, run_oracle  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -35,6 +35,7 @@ def _check(e):
     print({k: f"{v:.3e}" for k, v in e.items()}, flush=True)
     for k in ("u", "Q", "rho", "pos"):
         assert e[k] <= TOL, (k, e[k])
+    check_increments(e)
 
 
 # L = 20: Wendland cells (side >= 2h + skin) hold 8.2 lattice particles, within
@@ -75,7 +76,7 @@ def test_random_state_ten_steps(seed, opts):
     print("wendland 10 steps", seed, opts, flush=True)
     o, _ = run_oracle(p, s0, 10)
     g, sim = gpu_run(p, s0, 10, {keymap[k]: v for k, v in opts.items()})
-    _check(field_errors(g, o, s0, L))
+    _check(field_errors(g, o, s0, L, 10))
     sim.close()
 
 
@@ -87,7 +88,7 @@ def test_forms(form, elastic):
     print("wendland form", form, "elastic", elastic, flush=True)
     o, _ = run_oracle(p, s0, 10)
     g, sim = gpu_run(p, s0, 10)
-    _check(field_errors(g, o, s0, L))
+    _check(field_errors(g, o, s0, L, 10))
     sim.close()
 
 
@@ -97,7 +98,7 @@ def test_c1_lattice_and_diagnostics():
     s0 = wl.state_for(cfg, 0)
     o, ost = run_oracle(p, s0, 10)
     g, sim = gpu_run(p, s0, 10)
-    _check(field_errors(g, o, s0, p.L))
+    _check(field_errors(g, o, s0, p.L, 10))
     dg, do = sim.diagnostics(0), oracle.diagnostics(p, ost)
     assert dg["ke"] == pytest.approx(do["ke"], rel=1e-5)
     assert dg["F"] == pytest.approx(do["F"], rel=1e-5)
