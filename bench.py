@@ -7,10 +7,14 @@ positions. One step = rebin check + the four pair passes (volume; gradients,
 molecular field, co-rotation and Q update; density filter and EoS; pressure,
 corrector, APD and next predictor), all on the GPU with the state resident.
 
-Prints one JSON line. `value` is particle-steps per second over exactly
---steps timed steps (bracketed by stream synchronisation); the per-kernel
-durations come from HIP events the library records on its own stream around
-every launch inside the same timed region.
+Prints one JSON line. `value` is the median over --reps repetitions (default
+5) of particle-steps per second over exactly --steps timed steps, each
+repetition bracketed by stream synchronisation; the per-kernel durations come
+from HIP events the library records on its own stream around every launch
+inside the same timed repetitions. For context the line also carries the same
+median without the events and with hipGraph replay of 10-step chunks, and the
+FP64 oracle timed on the host: all cores over whole steps of the same box, and
+one core over one step of a 1024 x 1024 box of the same physics.
 """
 import argparse
 import json
@@ -65,6 +69,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions of --steps steps (median reported)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--side", type=int, default=2048, help="lattice side (default: the 4.2M-particle box)")
     ap.add_argument("--tile", type=int, default=4)
@@ -74,7 +79,6 @@ def main():
                     help="smoothing kernel: the paper's quintic spline (default) or the Wendland C2 variant")
     ap.add_argument("--autotune", action="store_true", help="pick tile and lanes per particle by timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph-check", action="store_true", help="also time the hipGraph replay path")
     ap.add_argument("--workload", choices=("box", "ensemble", "diagnostics"), default="box",
                     help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch; "
                          "diagnostics: time each grid and Lagrangian diagnostic on the box")
@@ -121,33 +125,35 @@ def main():
         sim.step(2)
         sim.check()
 
+    def timed_reps(reps):
+        out = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(args.steps)
+            rc = sim.sync()
+            torch.cuda.synchronize()
+            out.append(time.perf_counter() - t0)
+            if rc != 0:
+                raise SystemExit(f"device error {rc}: {P.strerror(rc)}")
+        return out
+
+    # the timed region: per-launch HIP events on the library's stream (eager launches)
     sim.set_option(P.NEM_OPT_TIMING, 1)
     sim.pass_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    rc = sim.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if rc != 0:
-        raise SystemExit(f"device error {rc}: {P.strerror(rc)}")
+    rep_s = timed_reps(args.reps)
     ms_pass, cnt = sim.pass_times(reset=True)
     sim.set_option(P.NEM_OPT_TIMING, 0)
-    elapsed = t1 - t0
+    elapsed = float(np.median(rep_s))
     value = n * args.steps / elapsed
     avg = {name: (ms_pass[i] / cnt[i] if cnt[i] else None) for i, name in enumerate(P.PASS_NAMES)}
-
-    graph_value = None
-    if args.graph_check:
-        sim.set_option(P.NEM_OPT_GRAPH, 1)
-        sim.step(2)
-        sim.check()
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        sim.step(args.steps)
-        sim.check()
-        g1 = time.perf_counter()
-        graph_value = n * args.steps / (g1 - g0)
+    # context: the same without events, and with graph replay of 10-step chunks
+    plain_value = n * args.steps / float(np.median(timed_reps(args.reps)))
+    sim.set_option(P.NEM_OPT_GRAPH, 10)
+    sim.step(10)
+    sim.check()
+    graph_value = n * args.steps / float(np.median(timed_reps(args.reps)))
+    sim.set_option(P.NEM_OPT_GRAPH, 0)
 
     # dominant kernel: the longest average launch
     dom = max((k for k in FLOP_PER_PAIR if avg.get(k)), key=lambda k: avg[k])
@@ -161,14 +167,18 @@ def main():
         flops_step = sum(NEIGHBOURS * FLOP_PER_PAIR[k] + FLOP_PER_PARTICLE[k] for k in FLOP_PER_PAIR)
 
     traffic = None
-    hbm_measured = None
+    hbm_counters = None
     if (args.kernel == "quintic" and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]
             and (cfg["n_side"], args.tile, args.lpp, args.comp) == MEASURED_TRAFFIC["config"]):
         tb = MEASURED_TRAFFIC["bytes"]
         traffic = tb[dom]
-        hbm_measured = {"GB/s": sum(tb.values()) / (sum(avg[k] for k in tb) * 1e-3) / 1e9,
+        # bytes per launch from the recorded counter runs of the same kernel sources,
+        # over the pass times of this run
+        hbm_counters = {"GB/s": sum(tb.values()) / (sum(avg[k] for k in tb) * 1e-3) / 1e9,
                         "frac": sum(tb.values()) / (sum(avg[k] for k in tb) * 1e-3) / HBM_PEAK,
-                        "bytes_per_step": sum(tb.values())}
+                        "bytes_per_step": sum(tb.values()),
+                        "source": "profiles/step_2048box_hbm_counters.md (rocprofv3 FETCH_SIZE and WRITE_SIZE "
+                                  "of the same kernel sources, copy-calibrated)"}
 
     if args.kernel == "quintic":
         roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
@@ -189,6 +199,7 @@ def main():
         cpu = {"value": n * done / (c1 - c0), "unit": "particle-steps/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": f"{done} steps of the same {cfg['n_side']}x{cfg['n_side']} box "
                                            f"from its initial state ({c1 - c0:.1f} s, FP64 C + OpenMP)"}
+        cpu.update(oracle_one_core(p))
 
     out = {
         "metric": METRIC,
@@ -208,13 +219,16 @@ def main():
                    "particles": n, "tile": args.tile, "lanes_per_particle": args.lpp,
                    "compensation": args.comp},
         "roofline": roofline,
-        "hbm_measured": hbm_measured,
+        "repetitions": args.reps,
+        "ms_per_step_reps": [1e3 * t / args.steps for t in rep_s],
+        "value_without_events": plain_value,
+        "graph_value": graph_value,
+        "hbm_counters": hbm_counters,
         "hbm_frac_algorithmic": value * bytes_step / HBM_PEAK,
         "valu_frac_algorithmic": value * flops_step / FP32_PEAK if flops_step else None,
         "bytes_per_particle_step": bytes_step,
         "flop_per_particle_step": flops_step,
         "kernel_ms": avg,
-        "graph_value": graph_value,
         "cpu_baseline": cpu,
     }
     sim.close()
@@ -226,6 +240,26 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+def oracle_one_core(p):
+    """The oracle on one host core (a child process with OMP_NUM_THREADS=1,
+    which touches no GPU): one step of a 1024 x 1024 box of the same physics
+    (same density, kernel and parameters, so the same work per particle-step
+    as the 2048 x 2048 box)."""
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r); import oracle, workloads as wl; "
+            "p = wl.Params(L=1024.0, zeta=%r, K=%r, dt=%r); "
+            "st = oracle.State(wl.initial_state(1024, 1.0, 1.0, 0, 'isotropic')); "
+            "t0 = time.perf_counter(); oracle.step(p, st, 1); t = time.perf_counter() - t0; "
+            "print(json.dumps([oracle.num_threads(), t]))") % (ROOT, p.zeta, p.K, p.dt)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"value_1core": None, "sample_1core": f"failed: {r.stderr[-300:]}"}
+    threads, t = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value_1core": 1024 * 1024 / t, "cores_1core": threads,
+            "sample_1core": f"1 step of a 1024x1024 box of the same physics on {threads} core ({t:.1f} s)"}
 
 
 def diagnostics(args):
@@ -279,7 +313,11 @@ def diagnostics(args):
 def ensemble(args):
     """32 replicas, sides drawn from U{128..384} (seeded), zeta x K sweep x 2
     seeds, advanced together: one launch per pass over the tiles of all
-    replicas, autotuned launch shape, steps replayed from a captured graph."""
+    replicas, launch shape (tile, lanes per particle, persistent grid) picked
+    by the autotuner, steps replayed from a captured graph of 10 steps. The
+    median of --reps repetitions; the same with a persistent grid forced off
+    and on for comparison."""
+    import numpy as np
     import torch
     import workloads as wl
     import paper_2108_08919_amd as P
@@ -291,23 +329,40 @@ def ensemble(args):
         sim.set_state(i, wl.state_for(r))
     sim.step(2)
     tile, lpp, _ = sim.autotune(3)
+    persist = sim.get_option(P.NEM_OPT_PERSIST)
     sim.set_option(P.NEM_OPT_GRAPH, 10)
     sim.step(args.warmup)
     sim.check()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    rc = sim.sync()
-    t1 = time.perf_counter()
-    if rc != 0:
-        raise SystemExit(f"device error {rc}: {P.strerror(rc)}")
     N = sum(ns)
-    value = N * args.steps / (t1 - t0)
+
+    def median_value():
+        out = []
+        for _ in range(args.reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(args.steps)
+            rc = sim.sync()
+            torch.cuda.synchronize()
+            out.append(time.perf_counter() - t0)
+            if rc != 0:
+                raise SystemExit(f"device error {rc}: {P.strerror(rc)}")
+        return N * args.steps / float(np.median(out)), out
+
+    value, rep_s = median_value()
+    by_grid = {}
+    for g in (0, 1024):
+        sim.set_option(P.NEM_OPT_PERSIST, g)
+        sim.set_option(P.NEM_OPT_GRAPH, 10)
+        sim.step(10)
+        by_grid[str(g)] = median_value()[0]
     out = {"metric": "SPH particle-steps/s, batched ensemble", "value": value, "unit": "particle-steps/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "repetitions": args.reps,
+           "ms_per_step": 1e3 * float(np.median(rep_s)) / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{len(reps)} replicas, sides U{{128..384}}, {N} particles, zeta x K sweep",
-                      "particles": N, "tile": tile, "lanes_per_particle": lpp, "graph_steps": 10},
+                      "particles": N, "tile": tile, "lanes_per_particle": lpp, "persistent_grid": persist,
+                      "graph_steps": 10},
+           "value_by_persistent_grid": by_grid,
            "hbm_frac_algorithmic": value * sum(BYTES_PER_PARTICLE.values()) / HBM_PEAK}
     sim.close()
     print(json.dumps(out), flush=True)

@@ -273,11 +273,18 @@ int nem_mixing(nem_sim* s, int32_t r, const uint8_t* colour, int32_t ncol, int32
 #define NEM_OPT_GRAPH 5
 #define NEM_OPT_PERSIST 6
 int nem_set_option(nem_sim* s, int32_t key, int64_t value);
+/* Current value of an option (NEM_E_INVAL for an unknown key). */
+int nem_get_option(nem_sim* s, int32_t key, int64_t* value);
 
-/* Autotuner: times `steps` steps of every supported (tile side, lanes per
- * particle) pair on the current state of all replicas (restoring the state
- * after each trial), keeps the fastest and returns it (*tile, *lpp, and the
- * best ms per step; each may be NULL). Allocates a state snapshot (hipMalloc). */
+/* Autotuner: times `steps` steps of every supported combination of tile side
+ * (4, 8), lanes per particle (1, 2, 4) and persistent grid (0 = one workgroup
+ * per tile; 512, 1024, 2048 workgroups looping over the tiles) on the current
+ * state of all replicas (restoring the state after each trial), keeps the
+ * fastest and returns it (*tile, *lpp, and the best ms per step; each may be
+ * NULL; the grid is read back with nem_get_option(NEM_OPT_PERSIST)). Each
+ * trial is the fastest of three timings of `steps` steps after a warm-up step;
+ * the search starts with 8 untimed steps. Allocates a state snapshot
+ * (hipMalloc). */
 int nem_autotune(nem_sim* s, int32_t steps, int32_t* tile, int32_t* lpp, double* ms_per_step);
 
 /* Accumulated kernel times (ms, from HIP events recorded on the library's

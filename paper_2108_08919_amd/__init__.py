@@ -45,7 +45,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
             "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list",
-            "nem_defects_noalloc")
+            "nem_defects_noalloc", "nem_get_option")
 
 
 class NemParams(C.Structure):
@@ -125,6 +125,8 @@ def lib(path: Optional[str] = None):
     L.nem_mixing.argtypes = [vp, C.c_int32, C.POINTER(C.c_uint8), C.c_int32, C.c_int32, C.POINTER(C.c_int64), dp]
     L.nem_set_option.restype = C.c_int
     L.nem_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+    L.nem_get_option.restype = C.c_int
+    L.nem_get_option.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
     L.nem_pass_times.restype = C.c_int
     L.nem_pass_times.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     fp = C.POINTER(C.c_float)
@@ -337,6 +339,12 @@ def nem_mixing(h, r, colour, ncol, B):
 
 def nem_set_option(h, key: int, value: int):
     _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
+
+
+def nem_get_option(h, key: int) -> int:
+    v = C.c_int64(0)
+    _check(h, lib().nem_get_option(C.c_void_p(h), key, C.byref(v)), "nem_get_option")
+    return v.value
 
 
 def nem_pass_times(h, reset: bool = False):
@@ -557,6 +565,9 @@ class Sim:
 
     def set_option(self, key: int, value: int):
         nem_set_option(self.h, key, value)
+
+    def get_option(self, key: int) -> int:
+        return nem_get_option(self.h, key)
 
     def pass_times(self, reset: bool = False):
         return nem_pass_times(self.h, reset)

@@ -1029,6 +1029,19 @@ int nem_set_option(nem_sim* s, int32_t key, int64_t value) {
   }
 }
 
+int nem_get_option(nem_sim* s, int32_t key, int64_t* value) {
+  if (!s || !value) return NEM_E_INVAL;
+  switch (key) {
+    case NEM_OPT_TILE: *value = s->T; return NEM_OK;
+    case NEM_OPT_LPP: *value = s->LPP; return NEM_OK;
+    case NEM_OPT_COMP: *value = s->COMP; return NEM_OK;
+    case NEM_OPT_TIMING: *value = s->timing; return NEM_OK;
+    case NEM_OPT_GRAPH: *value = s->use_graph ? s->graph_steps : 0; return NEM_OK;
+    case NEM_OPT_PERSIST: *value = s->persist; return NEM_OK;
+    default: return NEM_E_INVAL;
+  }
+}
+
 int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset) {
   if (!s) return NEM_E_INVAL;
   collect_times(s);

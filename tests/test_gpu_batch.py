@@ -1,6 +1,7 @@
 """Batched replicas: uneven boxes over a (zeta, K) sweep in one launch per pass,
 with hipGraph replay of step chunks, persistent pass kernels and the
-autotuner; each replica must equal its solo run."""
+autotuner; each replica must equal its solo run, and the 32 replicas of the
+batched workload (sides drawn from U{128..384}) must each match the oracle."""
 import os
 import sys
 
@@ -10,7 +11,7 @@ import pytest
 import workloads as wl
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import gpu_run, random_state  # noqa: E402
+from gpu_common import check_increments, field_errors, gpu_run, random_state, run_oracle  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +68,8 @@ def test_autotune_keeps_state():
     before = [sim.get_state(r) for r in range(len(reps))]
     t, l, ms = sim.autotune(3)
     assert t in (4, 8) and l in (1, 2, 4) and ms > 0
+    assert sim.get_option(P.NEM_OPT_PERSIST) in (0, 512, 1024, 2048)
+    assert (sim.get_option(P.NEM_OPT_TILE), sim.get_option(P.NEM_OPT_LPP)) == (t, l)
     after = [sim.get_state(r) for r in range(len(reps))]
     for a, b in zip(before, after):
         for k in a:
@@ -74,3 +77,58 @@ def test_autotune_keeps_state():
     sim.step(3)
     sim.check()
     sim.close()
+
+
+def test_ensemble_draw_against_oracle():
+    """The batched workload itself: 32 replicas with sides drawn from
+    U{128..384} (seeded), zeta x K sweep x 2 seeds, isotropic starts, advanced
+    10 steps in one launch per pass with a persistent grid and graph replay;
+    every replica against its own oracle run, to the fields' and increments'
+    bars of the single-box tests."""
+    import paper_2108_08919_amd as P
+    reps = wl.ensemble(0)
+    sides = [r["n_side"] for r in reps]
+    assert len(reps) == 32 and min(sides) >= 128 and max(sides) <= 384
+    states = [wl.state_for(r) for r in reps]
+    sim = P.Sim([r["params"] for r in reps], [s["x"].size for s in states])
+    sim.set_option(P.NEM_OPT_PERSIST, 1024)
+    sim.set_option(P.NEM_OPT_GRAPH, 5)
+    for i, s in enumerate(states):
+        sim.set_state(i, s)
+    sim.step(10)
+    sim.check()
+    worst = {}
+    for i, (r, s0) in enumerate(zip(reps, states)):
+        print("replica", i, "side", r["n_side"], "zeta", r["params"].zeta, "K", r["params"].K, flush=True)
+        o, _ = run_oracle(r["params"], s0, 10)
+        e = field_errors(sim.get_state(i), o, s0, r["params"].L, 10)
+        for k in ("u", "Q", "rho", "pos"):
+            assert e[k] <= 1e-5, (i, k, e[k])
+        check_increments(e)
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    print({k: f"{v:.3e}" for k, v in worst.items()}, flush=True)
+    sim.close()
+
+
+def test_persistent_grid_equals_dispatch():
+    """The same batch with one workgroup per tile and with persistent grids of
+    several sizes: identical results (the work list is walked in the same
+    per-tile order either way)."""
+    import paper_2108_08919_amd as P
+    reps = sweep(5, 2)
+    out = []
+    for g in (0, 300, 1024):
+        sim = P.Sim([p for p, _ in reps], [s["x"].size for _, s in reps])
+        sim.set_option(P.NEM_OPT_PERSIST, g)
+        assert sim.get_option(P.NEM_OPT_PERSIST) == g
+        for r, (_, s) in enumerate(reps):
+            sim.set_state(r, s)
+        sim.step(8)
+        sim.check()
+        out.append([sim.get_state(r) for r in range(len(reps))])
+        sim.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
