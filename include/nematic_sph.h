@@ -302,9 +302,11 @@ int nem_pass_times(nem_sim* s, double* ms, int64_t* launches, int32_t reset);
  * with FP32 accumulation, trained on samples the solver generates, with mult
  * plain steps of dt as the fallback.
  *
- * Inputs per particle (12): Qxx, Qxy, Qyy, du_x/dx, du_x/dy, du_y/dx, du_y/dy,
- * Hxx, Hxy, Hyy, (rho - rho0)/rho0, zeta, taken in pass B of the macro step;
- * outputs (5): corrections of Qxx, Qxy, Qyy, u_x, u_y (Q projected traceless).
+ * Inputs per particle (12): Qxx, Qxy, du_x/dx, du_x/dy, du_y/dx, du_y/dy,
+ * Hxx, Hxy, (rho - rho0)/rho0, zeta (taken in pass B of the macro step) and
+ * the step's change of acceleration a^{n+1/2} - a^{n-1/2} (x, y; from pass D),
+ * which drives the velocity error of the lagged predictor; outputs (5):
+ * corrections of Qxx, Qxy, Qyy, u_x, u_y (Q projected traceless).
  * Inputs and targets are z-scored with stored means and standard deviations.
  * Weights: flat FP32 vector W1 (12x64, input-major), b1, W2 (64x64), b2,
  * W3 (64x5), b3 (nem_mlp_nparams() values). Device pointers (X, T, Y) are
@@ -330,6 +332,17 @@ int nem_mlp_grad(nem_mlp* m, const float* X, const float* T, int64_t n, float* g
  * samples (a deterministic per-epoch permutation); *final_loss = last batch. */
 int nem_mlp_train(nem_mlp* m, const float* X, const float* T, int64_t n, int32_t epochs, int32_t batch,
                   double lr, double* final_loss);
+/* Network evaluated on X (n x 12): *max_norm (may be NULL) = the largest norm
+ * of its correction in normalised output units (the quantity nem_step_learned
+ * compares with tau); rel_mse[5] (may be NULL; then T may be NULL) = per output
+ * the mean squared error against T (n x 5) relative to T's variance (1: no
+ * better than no correction). FP64 sums in a fixed order. Allocates a buffer
+ * for the predictions (hipMalloc). */
+int nem_mlp_eval(nem_mlp* m, const float* X, const float* T, int64_t n, double* rel_mse, double* max_norm);
+/* Switch off the outputs o with off[o] != 0 (5 flags): their last-layer weights,
+ * bias and output mean become zero, so the network returns exactly zero for
+ * them. Resets Adam. */
+int nem_mlp_mask_outputs(nem_mlp* m, const int32_t* off);
 void nem_mlp_destroy(nem_mlp* m);
 
 /* Training samples at the current state of every replica, particle
@@ -337,6 +350,10 @@ void nem_mlp_destroy(nem_mlp* m);
  * = (Q, u after mult steps of dt) - (Q, u after one step of mult*dt). The
  * state is left unchanged. Allocates a scratch buffer (hipMalloc). */
 int nem_samples(nem_sim* s, int32_t mult, float* X, float* T);
+/* The same for the selected rows only: row k of X (nrows x 12) and T
+ * (nrows x 5) is particle rows[k] (host array, part_base(r) + id, each in
+ * [0, total particles)). Allocates scratch buffers (hipMalloc). */
+int nem_samples_rows(nem_sim* s, int32_t mult, const int64_t* rows, int64_t nrows, float* X, float* T);
 /* n_macro macro steps of mult*dt with corrections; a macro step whose largest
  * correction norm (normalised units) exceeds tau is replayed as mult steps of
  * dt. Synchronises once per macro step (one word read back); allocates

@@ -45,7 +45,7 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
             "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list",
-            "nem_defects_noalloc", "nem_get_option")
+            "nem_defects_noalloc", "nem_get_option", "nem_mlp_eval", "nem_mlp_mask_outputs", "nem_samples_rows")
 
 
 class NemParams(C.Structure):
@@ -148,6 +148,12 @@ def lib(path: Optional[str] = None):
     L.nem_mlp_destroy.argtypes = [vp]
     L.nem_samples.restype = C.c_int
     L.nem_samples.argtypes = [vp, C.c_int32, vp, vp]
+    L.nem_samples_rows.restype = C.c_int
+    L.nem_samples_rows.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.c_int64, vp, vp]
+    L.nem_mlp_eval.restype = C.c_int
+    L.nem_mlp_eval.argtypes = [vp, vp, vp, C.c_int64, dp, dp]
+    L.nem_mlp_mask_outputs.restype = C.c_int
+    L.nem_mlp_mask_outputs.argtypes = [vp, C.POINTER(C.c_int32)]
     L.nem_step_learned.restype = C.c_int
     L.nem_step_learned.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_double, C.POINTER(C.c_int64), dp]
     L.nem_autotune.restype = C.c_int
@@ -429,6 +435,21 @@ class Mlp:
                                     X.shape[0], epochs, batch, lr, C.byref(loss)), "nem_mlp_train")
         return loss.value
 
+    def evaluate(self, X, T=None):
+        """(per-output relative MSE against T or None, largest predicted
+        correction norm in normalised units) on the device inputs X."""
+        rel = np.zeros(self.NO) if T is not None else None
+        mx = C.c_double(0)
+        _mcheck(lib().nem_mlp_eval(C.c_void_p(self.h), C.c_void_p(X.data_ptr()),
+                                   C.c_void_p(T.data_ptr()) if T is not None else None, X.shape[0],
+                                   _dp(rel) if rel is not None else None, C.byref(mx)), "nem_mlp_eval")
+        return (rel.tolist() if rel is not None else None), mx.value
+
+    def mask_outputs(self, outputs):
+        """Switch off the given output components (they return exactly zero)."""
+        off = (C.c_int32 * self.NO)(*[1 if o in set(outputs) else 0 for o in range(self.NO)])
+        _mcheck(lib().nem_mlp_mask_outputs(C.c_void_p(self.h), off), "nem_mlp_mask_outputs")
+
     def close(self):
         if getattr(self, "h", None):
             lib().nem_mlp_destroy(C.c_void_p(self.h))
@@ -546,6 +567,22 @@ class Sim:
         T = torch.empty((N, 5), dtype=torch.float32, device=self.device)
         _check(self.h, lib().nem_samples(C.c_void_p(self.h), mult, C.c_void_p(X.data_ptr()),
                                          C.c_void_p(T.data_ptr())), "nem_samples")
+        return X, T
+
+    def samples_rows(self, rows, mult: int = 4, X=None, T=None):
+        """Training inputs and targets of the particles `rows` (indices into all
+        replicas' particles, part_base + id) only, into X and T when given
+        (contiguous device tensors of len(rows) x 12 and x 5)."""
+        import torch
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        if X is None:
+            X = torch.empty((rows.size, 12), dtype=torch.float32, device=self.device)
+        if T is None:
+            T = torch.empty((rows.size, 5), dtype=torch.float32, device=self.device)
+        assert X.is_contiguous() and T.is_contiguous() and X.shape == (rows.size, 12) and T.shape == (rows.size, 5)
+        _check(self.h, lib().nem_samples_rows(C.c_void_p(self.h), mult, rows.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              rows.size, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr())),
+               "nem_samples_rows")
         return X, T
 
     def step_learned(self, mlp: "Mlp", n_macro: int, mult: int = 4, tau: float = 1e30):

@@ -210,6 +210,50 @@ __global__ void k_copy_list(CopyList L) {
   }
 }
 
+// Per-output statistics of targets T and predictions Y (n x 5) in FP64, one
+// workgroup per output, a fixed summation order (deterministic):
+// out[3o] = mean of T_o, out[3o + 1] = variance of T_o, out[3o + 2] = mean of
+// (T_o - Y_o)^2.
+__global__ __launch_bounds__(256) void k_eval_stats(const float* T, const float* Y, int64_t n, double* out) {
+  const int o = blockIdx.x;
+  __shared__ double sh[2][256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)T[i * 5 + o];
+  sh[0][threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) sh[0][threadIdx.x] += sh[0][threadIdx.x + d];
+    __syncthreads();
+  }
+  const double mean = sh[0][0] / (double)n;
+  __syncthreads();
+  double v = 0.0, e = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double t = (double)T[i * 5 + o];
+    const double dv = t - mean, de = t - (double)Y[i * 5 + o];
+    v += dv * dv;
+    e += de * de;
+  }
+  sh[0][threadIdx.x] = v;
+  sh[1][threadIdx.x] = e;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) { sh[0][threadIdx.x] += sh[0][threadIdx.x + d]; sh[1][threadIdx.x] += sh[1][threadIdx.x + d]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[3 * o] = mean; out[3 * o + 1] = sh[0][0] / (double)n; out[3 * o + 2] = sh[1][0] / (double)n; }
+}
+
+// dst[k * w + c] = src[rows[k] * w + c] for the selected rows.
+__global__ void k_gather_rows(const float* src, const int64_t* rows, int64_t nrows, int w, int64_t nsrc, float* dst,
+                              unsigned* flags) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nrows; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = rows[k];
+    if (r < 0 || r >= nsrc) { atomicOr(flags, ERR_RANGE); continue; }
+    for (int c = 0; c < w; ++c) dst[k * w + c] = src[r * w + c];
+  }
+}
+
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
 
 // (chunks, replicas) grid for the per-replica kernels.
@@ -543,8 +587,95 @@ void nem_mlp_destroy(nem_mlp* m) {
   delete m;
 }
 
+int nem_mlp_eval(nem_mlp* m, const float* X, const float* T, int64_t n, double* rel_mse, double* max_norm) {
+  if (!m || !X || n < 1 || (rel_mse && !T)) return NEM_E_INVAL;
+  float* Y = nullptr;
+  unsigned* mx = nullptr;
+  MLPCHK(hipMalloc((void**)&Y, sizeof(float) * 5 * (size_t)n));
+  if (hipMalloc((void**)&mx, sizeof(unsigned)) != hipSuccess) { hipFree(Y); m->err = "hipMalloc (max norm)"; return NEM_E_HIP; }
+  hipError_t e = hipMemsetAsync(mx, 0, sizeof(unsigned), m->stream);
+  if (e == hipSuccess) {
+    launch_mlp_forward(m->P, m->hnorm, X, n, Y, mx, m->stream);
+    if (rel_mse) hipLaunchKernelGGL(k_eval_stats, dim3(5), dim3(256), 0, m->stream, T, (const float*)Y, n, m->stats);
+    e = hipGetLastError();
+  }
+  double st[15];
+  unsigned hm = 0;
+  if (e == hipSuccess && rel_mse) e = hipMemcpyAsync(st, m->stats, sizeof(st), hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hm, mx, sizeof(hm), hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  hipFree(Y);
+  hipFree(mx);
+  if (e != hipSuccess) return mlp_fail(m, e, "nem_mlp_eval");
+  if (rel_mse)
+    for (int o = 0; o < 5; ++o) rel_mse[o] = st[3 * o + 1] > 0.0 ? st[3 * o + 2] / st[3 * o + 1] : NAN;
+  if (max_norm) {
+    float f;
+    std::memcpy(&f, &hm, sizeof(f));
+    *max_norm = f;
+  }
+  return NEM_OK;
+}
+
+int nem_mlp_mask_outputs(nem_mlp* m, const int32_t* off) {
+  if (!m || !off) return NEM_E_INVAL;
+  const int np = mlp_nparam();
+  std::vector<float> w(np);
+  int rc = nem_mlp_get_weights(m, w.data());
+  if (rc) return rc;
+  // flat layout: W1 (12 x 64), b1, W2 (64 x 64), b2, W3 (64 x 5, input-major), b3
+  const int off_w3 = 12 * 64 + 64 + 64 * 64 + 64, off_b3 = off_w3 + 64 * 5;
+  float nm[34];
+  std::memcpy(nm, m->hnorm, sizeof(nm));
+  for (int o = 0; o < 5; ++o) {
+    if (!off[o]) continue;
+    for (int i = 0; i < 64; ++i) w[off_w3 + i * 5 + o] = 0.0f;
+    w[off_b3 + o] = 0.0f;
+    nm[24 + o] = 0.0f;   // output mean: the component is exactly zero
+  }
+  rc = nem_mlp_set_weights(m, w.data());
+  if (rc) return rc;
+  return nem_mlp_set_norm(m, nm);
+}
+
+// Training samples of all particles into X (ntot x 12) and T (ntot x 5).
+static int samples_into(nem_sim* s, int32_t mult, float* X, float* T);
+
 int nem_samples(nem_sim* s, int32_t mult, float* X, float* T) {
   if (!s || mult < 2 || !X || !T) return NEM_E_INVAL;
+  return samples_into(s, mult, X, T);
+}
+
+int nem_samples_rows(nem_sim* s, int32_t mult, const int64_t* rows, int64_t nrows, float* X, float* T) {
+  if (!s || mult < 2 || !rows || nrows < 1 || !X || !T) return NEM_E_INVAL;
+  const size_t N = (size_t)s->ntot;
+  float *xa = nullptr, *ta = nullptr;
+  int64_t* dr = nullptr;
+  int rc = NEM_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == NEM_OK) rc = hip_fail(s, e, what);
+  };
+  chk(hipMalloc((void**)&xa, sizeof(float) * 12 * N), "hipMalloc (samples)");
+  chk(hipMalloc((void**)&ta, sizeof(float) * 5 * N), "hipMalloc (samples)");
+  chk(hipMalloc((void**)&dr, sizeof(int64_t) * (size_t)nrows), "hipMalloc (rows)");
+  if (!rc) chk(hipMemcpyAsync(dr, rows, sizeof(int64_t) * (size_t)nrows, hipMemcpyHostToDevice, s->stream), "rows");
+  if (!rc) rc = samples_into(s, mult, xa, ta);
+  if (!rc) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nrows)), dim3(256), 0, s->stream, (const float*)xa,
+                       (const int64_t*)dr, nrows, 12, (int64_t)N, X, s->flags);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nrows)), dim3(256), 0, s->stream, (const float*)ta,
+                       (const int64_t*)dr, nrows, 5, (int64_t)N, T, s->flags);
+    chk(hipGetLastError(), "k_gather_rows");
+  }
+  hipStreamSynchronize(s->stream);
+  hipFree(xa);
+  hipFree(ta);
+  hipFree(dr);
+  if (rc) return rc;
+  return check_flags(s);
+}
+
+static int samples_into(nem_sim* s, int32_t mult, float* X, float* T) {
   if (s->hp[0].q3d) { s->err = "the learned corrector covers the 2x2 Q only"; return NEM_E_INVAL; }
   for (int r = 0; r < s->R; ++r)
     if (!s->has_state[r]) return NEM_E_STATE;

@@ -572,12 +572,12 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
         const float QH = 2.0f * (qa * Ha + qb * Hb);
         a.pi[g] = make_float2(R.lam * (2.0f * QH * qa - Ha), R.lam * (2.0f * QH * qb - Hb));
       }
-      if (Q3 == 0 && a.feat) {  // learned-corrector inputs (storage order): Q, grad u, H, density, activity
+      if (Q3 == 0 && a.feat) {  // learned-corrector inputs 0-9 (storage order): Q, grad u, H, density, activity
         float* f = a.feat + (size_t)g * 12;
-        f[0] = qa; f[1] = qb; f[2] = -qa;
-        f[3] = G11; f[4] = G12; f[5] = G21; f[6] = G22;
-        f[7] = Ha; f[8] = Hb; f[9] = -Ha;
-        f[10] = drho_n * R.inv_rho0; f[11] = R.zeta;
+        f[0] = qa; f[1] = qb;
+        f[2] = G11; f[3] = G12; f[4] = G21; f[5] = G22;
+        f[6] = Ha; f[7] = Hb;
+        f[8] = drho_n * R.inv_rho0; f[9] = R.zeta;
       }
     }
   }
@@ -778,6 +778,11 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
         const float r0 = gr / (float)cnt;   // mean neighbour distance
         const float f = r0 * r0 * a.uv[g] * R.dt;
         drx = f * gx; dry = f * gy;
+      }
+      if (a.feat) {   // learned-corrector inputs 10-11: the step's change of acceleration a^{n+1/2} - a^{n-1/2}
+        const float2 ao = a.acc[g];
+        float* f = a.feat + (size_t)g * 12;
+        f[10] = ax - ao.x; f[11] = ay - ao.y;
       }
       const float unx = u1x + hdt * ax, uny = u1y + hdt * ay;      // u^{n+3/2}
       // r^{n+1} - r^{n+1/2}: u^{n+1} dt/2 (kick-drift-kick) or u^{n+1/2} dt/2

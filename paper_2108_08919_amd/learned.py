@@ -1,32 +1,41 @@
 """Learned corrector: training data from the solver, training, evaluation.
 
-Every numerical step runs in the library (nem_samples, nem_mlp_fit_norm,
-nem_mlp_train, nem_step_learned, nem_diagnostics, nem_defects); this module
-only schedules the calls and collects the results.
+Every numerical step runs in the library (nem_samples_rows, nem_mlp_fit_norm,
+nem_mlp_train, nem_mlp_eval, nem_mlp_mask_outputs, nem_step_learned,
+nem_diagnostics, nem_defects); this module only schedules the calls, draws the
+seeded parameters and sample rows, and collects the results (torch supplies
+device memory).
 
 Workloads:
 * training: 16 replicas of a 256 x 256 lattice box with (zeta, K) drawn from
-  U[0.005, 0.04] x U[0.01, 0.08] (seeded), isotropic director start; at four
-  times t in {0.25, 0.75, 1.25, 1.75} every replica contributes the inputs and
-  the (4 dt fine) - (one 4 dt step) targets of a seeded subset of 16,384 of its
-  particles: 4 x 16 x 16,384 = 1,048,576 samples;
-* held out: 4 more replicas from other seeds, same recipe; the network's mean
-  squared error per output relative to the output's variance (1 = no better
-  than no correction);
+  U[0.005, 0.04] x U[0.01, 0.08] (seeded), isotropic director start, advanced
+  by macro steps of mult*dt without corrections (a network of zeros), the way a
+  learned run advances; at six times t in {0.02, 0.1, 0.25, 0.75, 1.25, 1.75}
+  (the first two in the transient that follows the start from rest) every
+  replica contributes the inputs and the (mult steps of dt) - (one step of
+  mult*dt) targets of a seeded subset of 10,923 of its particles:
+  6 x 16 x 10,923 = 1,048,608 samples. Coarse trajectories matter for the
+  velocity inputs: the change of acceleration over a step spans the previous
+  macro step, as it does in a learned run;
+* held out: 4 more replicas from other seeds, same recipe, every particle;
+  the network's mean squared error per output relative to the output's
+  variance (1 = no better than no correction), and the largest correction norm
+  it predicts on these states;
 * evaluation: the 1024 x 1024 box at zeta = K = 0.02 over t in [0, 2] from four
   seeded isotropic starts: plain steps of dt = 1e-3 (reference), plain steps of
-  4 dt, and learned macro steps of 4 dt; the errors are those of the ensemble-
-  and time-averaged kinetic energy and defect density over t in [1, 2], and
-  the relative L2 errors of the final fields against the plain-dt run from the
-  same start (Q relative to its change over the run, u relative to its size).
+  mult dt, and learned macro steps of mult dt; the errors are those of the
+  ensemble- and time-averaged kinetic energy and defect density over t in
+  [1, 2], and the relative L2 errors of the final fields against the plain-dt
+  run from the same start (Q relative to its change over the run, u relative to
+  its size).
 
-The fallback threshold tau is the 99.9th percentile of the training
-corrections' norm in the network's normalised output units; a macro step whose
-largest predicted correction norm exceeds it is replayed as 4 fine steps.
 Output components with no skill on the held-out boxes (relative MSE not below
-1) are switched off before the evaluation, so they contribute no correction.
+1) are switched off before the evaluation. The fallback threshold tau is then
+TAU_MARGIN times the largest correction norm the network predicts on the
+held-out boxes: a macro step whose corrections go beyond anything the network
+produced on states of its training distribution is replayed as mult fine steps.
 
-Run: python -m paper_2108_08919_amd.learned  (prints one JSON line)
+Run: python -m paper_2108_08919_amd.learned [--mult 4]  (prints one JSON line)
 """
 from __future__ import annotations
 
@@ -36,6 +45,8 @@ import sys
 import time
 
 import numpy as np
+
+TAU_MARGIN = 1.5
 
 
 def _log(msg):
@@ -47,8 +58,22 @@ def _sim(params, n):
     return Sim(params, n)
 
 
-def training_set(side=256, replicas=16, times=(0.25, 0.75, 1.25, 1.75), per_replica=16384, mult=4, seed=0,
-                 dt=1e-3):
+def zero_network():
+    """A network of zeros with identity normalisation: learned macro steps with
+    it are plain steps of mult*dt."""
+    from . import Mlp
+    m = Mlp()
+    m.set_weights(np.zeros(m.nparams, dtype=np.float32))
+    m.set_norm(np.concatenate([np.zeros(12), np.ones(12), np.zeros(5), np.ones(5)]).astype(np.float32))
+    return m
+
+
+TRAIN_TIMES = (0.02, 0.1, 0.25, 0.75, 1.25, 1.75)
+
+
+def training_set(side=256, replicas=16, times=TRAIN_TIMES, per_replica=10923, mult=4, seed=0, dt=1e-3):
+    """(X, T) on the device: seeded replicas advanced by uncorrected macro steps
+    of mult*dt; per_replica=None takes every particle."""
     import torch
     import workloads as wl
     rng = np.random.default_rng(seed)
@@ -59,26 +84,27 @@ def training_set(side=256, replicas=16, times=(0.25, 0.75, 1.25, 1.75), per_repl
         params.append(wl.Params(L=float(side), zeta=zeta, K=K, dt=dt))
         states.append(wl.initial_state(side, 1.0, 1.0, seed=2000 + 100 * seed + r, kind="isotropic"))
     n = side * side
+    take = n if per_replica is None else per_replica
     sim = _sim(params, [n] * replicas)
     for r in range(replicas):
         sim.set_state(r, states[r])
-    Xs, Ts = [], []
+    z = zero_network()
+    rows_per_time = replicas * take
+    X = torch.empty((len(times) * rows_per_time, 12), dtype=torch.float32, device=sim.device)
+    T = torch.empty((len(times) * rows_per_time, 5), dtype=torch.float32, device=sim.device)
     t = 0.0
-    for tk in times:
-        k = int(round((tk - t) / dt))
-        sim.step(k)
-        t = tk
-        X, T = sim.samples(mult)
-        pick = []
-        for r in range(replicas):
-            sel = rng.choice(n, per_replica, replace=False)
-            pick.append(torch.from_numpy(np.sort(sel) + r * n))
-        idx = torch.cat(pick).to(X.device)
-        Xs.append(X[idx])
-        Ts.append(T[idx])
+    for i, tk in enumerate(times):
+        k = int(round((tk - t) / (mult * dt)))
+        sim.step_learned(z, k, mult)
+        t += k * mult * dt
+        rows = np.concatenate([(np.arange(n) if per_replica is None else np.sort(rng.choice(n, take, replace=False)))
+                               + r * n for r in range(replicas)])
+        sl = slice(i * rows_per_time, (i + 1) * rows_per_time)
+        sim.samples_rows(rows, mult, X[sl], T[sl])
     sim.check()
     sim.close()
-    return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
+    z.close()
+    return X, T
 
 
 def init_weights(seed=0):
@@ -93,46 +119,34 @@ def init_weights(seed=0):
 
 
 def fit(X, T, epochs=20, batch=4096, lr=2e-3, seed=0):
-    """Train a network on (X, T); returns (mlp, final batch loss, tau) where tau
-    is the 99.9th percentile of the norm of the training corrections T in the
-    network's normalised output units (the fallback threshold)."""
-    import torch
+    """Train a network on (X, T); returns (mlp, final batch loss)."""
     from . import Mlp
     m = Mlp()
     m.set_weights(init_weights(seed))
     m.fit_norm(X, T)
     loss = m.train(X, T, epochs=epochs, batch=batch, lr=lr)
-    nm = torch.from_numpy(m.get_norm()).to(X.device)
-    z = (T - nm[24:29]) / nm[29:34]
-    tau = float(torch.quantile(z.norm(dim=1)[:: max(1, X.shape[0] // 200000)], 0.999).item())
-    return m, loss, tau
-
-
-def mask_unskilled(m, rel, threshold=1.0):
-    """Switch off the output components whose held-out relative MSE is not
-    below `threshold` (no better than no correction): their last-layer weights,
-    bias and output mean are set to zero, so the network returns exactly zero
-    for them. Returns the masked component indices."""
-    w = m.get_weights()
-    nm = m.get_norm()
-    off_w3 = 12 * 64 + 64 + 64 * 64 + 64          # W3 (64 x 5, input-major), then b3 (5)
-    off_b3 = off_w3 + 64 * 5
-    masked = [o for o, r in enumerate(rel) if not r < threshold]
-    for o in masked:
-        w[off_w3 + o: off_b3: 5] = 0.0
-        w[off_b3 + o] = 0.0
-        nm[24 + o] = 0.0
-    m.set_weights(w)
-    m.set_norm(nm)
-    return masked
+    return m, loss
 
 
 def held_out_errors(m, X, T):
     """Per-output mean squared error of the network on (X, T) relative to the
     variance of T (1 = no better than predicting the mean, 0 = exact)."""
-    Y = m.forward(X).double()
-    Td = T.double()
-    return (((Td - Y) ** 2).mean(0) / Td.var(0, unbiased=False)).tolist()
+    return m.evaluate(X, T)[0]
+
+
+def mask_unskilled(m, rel, threshold=1.0):
+    """Switch off the output components whose held-out relative MSE is not
+    below `threshold` (no better than no correction); returns their indices."""
+    masked = [o for o, r in enumerate(rel) if not r < threshold]
+    if masked:
+        m.mask_outputs(masked)
+    return masked
+
+
+def fallback_threshold(m, X):
+    """tau = TAU_MARGIN x the largest correction norm the (masked) network
+    predicts on the held-out inputs X."""
+    return TAU_MARGIN * m.evaluate(X)[1]
 
 
 def _observe(sim, side):
@@ -271,16 +285,18 @@ def main():
     X, T = training_set(mult=args.mult)
     t1 = time.perf_counter()
     _log(f"training set: {X.shape[0]} samples in {t1 - t0:.1f} s")
-    m, loss, tau = fit(X, T, epochs=args.epochs)
+    m, loss = fit(X, T, epochs=args.epochs)
     t2 = time.perf_counter()
-    _log(f"trained: loss {loss:.4g}, tau {tau:.3g}, {t2 - t1:.1f} s")
-    # held-out samples: other seeds, same recipe
-    Xh, Th = training_set(replicas=4, mult=args.mult, seed=1)
+    _log(f"trained: loss {loss:.4g}, {t2 - t1:.1f} s")
+    # held-out boxes: other seeds, same recipe, every particle
+    Xh, Th = training_set(replicas=4, mult=args.mult, seed=1, per_replica=None)
     rel = held_out_errors(m, Xh, Th)
     _log(f"held-out relative MSE per output (dQxx, dQxy, dQyy, dux, duy): {[round(v, 4) for v in rel]}")
     masked = mask_unskilled(m, rel)
     rel_masked = held_out_errors(m, Xh, Th)
-    _log(f"masked outputs {masked}; held-out relative MSE after masking {[round(v, 4) for v in rel_masked]}")
+    tau = fallback_threshold(m, Xh)
+    _log(f"masked outputs {masked}; held-out relative MSE after masking {[round(v, 4) for v in rel_masked]}; "
+         f"tau {tau:.4g}")
     ev = evaluate(m, tau, side=args.side, seeds=tuple(range(args.seeds)), mult=args.mult)
     t3 = time.perf_counter()
     print(json.dumps({"samples": int(X.shape[0]), "mult": args.mult, "train_loss": loss,
