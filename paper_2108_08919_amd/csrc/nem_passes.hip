@@ -66,27 +66,29 @@ __device__ __forceinline__ bool verlet_pair(uint32_t e, const float2* shift, int
 }
 
 // The 32-bit words of one particle's list (two 16-bit entries each, rows
-// `stride` words apart), each loaded two words before it is used. The register
-// copy w0 = w1 makes the compiler wait for a load at the top of the next
-// iteration, so one iteration's pair work overlaps each load's latency (a
+// `stride` words apart), each loaded DEPTH words before it is used. The
+// register copies w[i] = w[i + 1] make the compiler wait for a load DEPTH - 1
+// iterations after issuing it, so pair work overlaps each load's latency (a
 // load waited for at once left the passes stalled on HBM). Rows past the
 // particle's nw words are not loaded.
+template <int DEPTH>
 struct ListStream {
   const uint32_t* p;
   size_t stride;
   int nw, m;
-  uint32_t w0, w1;
+  uint32_t w[DEPTH];
   __device__ __forceinline__ ListStream(const uint32_t* p_, size_t stride_, int nwords)
-      : p(p_), stride(stride_), nw(nwords), m(2) {
-    w0 = nw > 0 ? p[0] : 0u;
-    w1 = nw > 1 ? p[stride] : 0u;
+      : p(p_), stride(stride_), nw(nwords), m(DEPTH) {
+#pragma unroll
+    for (int i = 0; i < DEPTH; ++i) w[i] = nw > i ? p[(size_t)i * stride] : 0u;
   }
   __device__ __forceinline__ uint32_t next() {
-    const uint32_t w = w0;
-    w0 = w1;
-    w1 = m < nw ? p[(size_t)m * stride] : 0u;
+    const uint32_t r = w[0];
+#pragma unroll
+    for (int i = 0; i + 1 < DEPTH; ++i) w[i] = w[i + 1];
+    w[DEPTH - 1] = m < nw ? p[(size_t)m * stride] : 0u;
     ++m;
-    return w;
+    return r;
   }
 };
 
@@ -100,7 +102,7 @@ __device__ __forceinline__ void each_listed(const uint32_t* __restrict__ nl, int
                                             int sub, Body&& body, Flush&& flush) {
   const uint32_t* p = nl + g;
   if (lpp == 1) {
-    ListStream ls(p, (size_t)ntot, (cnt + 1) >> 1);
+    ListStream<WPI == 2 ? 3 : 2> ls(p, (size_t)ntot, (cnt + 1) >> 1);
     int k = 0;
     if constexpr (WPI == 2) {
       for (; k + 3 < cnt; k += 4) {
@@ -419,7 +421,7 @@ __device__ __forceinline__ void tile_pass_b(const StepArgs& a, int w) {
       if constexpr (FORM == 1) ri = s_rho[p];
       const float ri2inv = 1.0f / (ri * ri);
       const int cnt = min(a.vcnt[g], KMAX);
-      each_listed(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      each_listed<2>(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         // entries outside the support are skipped (a branch measured faster
         // here than zeroing their terms with selects)
@@ -715,7 +717,7 @@ __device__ __forceinline__ void tile_pass_d(const StepArgs& a, int w) {
       float2 pii = {0.f, 0.f};
       if constexpr (EL == 1) pii = s_pi[p];
       const int cnt = min(a.vcnt[g], KMAX);
-      each_listed(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
+      each_listed<2>(a.vl, a.ntot, g, cnt, lpp, sub, [&](uint32_t e) {
         int j; float rx, ry, r2;
         if (!verlet_pair(e, L.shift, S - 1, s_off, oi, R.R2, j, rx, ry, r2)) return;   // as in pass B
         ++nacc;
@@ -1020,6 +1022,7 @@ __global__ __launch_bounds__(WG) void k_pass_a_walk(const StepArgs a) {
 template <int T, int COMP, int FORM, int EL, int KERN>
 struct Waves {
   static constexpr int B = ((T == 4 || KERN == 1) && (COMP == 0 || (COMP == 1 && FORM == 0))) ? 5 : 1;
+  static constexpr int C = 8;
   static constexpr int D = ((T == 4 || KERN == 1) && EL == 0) ? 8 : 1;
 };
 
@@ -1030,7 +1033,8 @@ void k_pass_b(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_b<T, COMP, FORM, EL, KERN, Q3>(a, w); __syncthreads(); }
 }
 template <int T, int COMP, int KERN>
-__global__ __launch_bounds__(WG) void k_pass_c(const StepArgs a) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(Waves<T, COMP, 0, 0, KERN>::C)))
+void k_pass_c(const StepArgs a) {
   for (int w = blockIdx.x; w < a.nwork; w += gridDim.x) { tile_pass_c<T, COMP, KERN>(a, w); __syncthreads(); }
 }
 template <int T, int COMP, int FORM, int EL, int KERN, int INTEG>
