@@ -40,7 +40,8 @@ def csr_rows(rp, col):
 
 
 @pytest.mark.parametrize("kind,L,seed", [("lattice", 16, 0), ("lattice", 64, 0), ("jitter", 24, 1),
-                                         ("uniform", 16, 2), ("uniform", 24, 3), ("uniform", 40, 4)])
+                                         ("uniform", 16, 2), ("uniform", 24, 3), ("uniform", 40, 4),
+                                         ("lattice", 12, 0), ("jitter", 12, 5)])
 def test_neighbors_bit_exact(kind, L, seed):
     import paper_2108_08919_amd as P
     p = wl.Params(L=float(L))
@@ -189,6 +190,24 @@ def test_random_state_ten_steps(seed, zeta):
     # and the fields keep their bars.
     check(e, dr_bar=3e-3 if seed == 2 else None)
     assert e["pos_abs_max"] < 5e-7
+    sim.close()
+
+
+def test_smallest_box_ten_steps():
+    """The smallest box the library accepts: three cells per side (L = 12,
+    cell side kappa h + skin = 4), so every stencil direction reaches the
+    box's other cells through the periodic wrap and the one tile of four
+    cells holds three."""
+    L = 12
+    p = wl.Params(L=float(L), zeta=0.03, K=0.04)
+    s0 = random_state(L, 3, amp_u=2e-3)
+    say("smallest box 10 steps", s0["x"].size)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    e = field_errors(g, o, s0, L, 10)
+    check(e)
+    assert e["pos_abs_max"] < 5e-7
+    _walked_list_matches_oracle(sim, p, L)
     sim.close()
 
 
