@@ -15,7 +15,8 @@ launch: the per-kernel durations come from it (its own rate is reported as
 value_with_events). For context the line also carries the median with hipGraph
 replay of 10-step chunks, and the FP64 oracle timed on the host: all cores over
 whole steps of the same box, and one core over one step of a 1024 x 1024 box of
-the same physics.
+the same physics; and the platform (device, architecture, HIP version, clock
+levels).
 """
 import argparse
 import json
@@ -234,6 +235,7 @@ def main():
         "flop_per_particle_step": flops_step,
         "kernel_ms": avg,
         "cpu_baseline": cpu,
+        "platform": platform(),
     }
     sim.close()
     if args.calib_copy_mib:
@@ -244,6 +246,29 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+def platform():
+    """The device, its architecture and compute units, the HIP version torch
+    was built with, and the clocks rocm-smi reports (current levels at the end
+    of the run; None where a query is not available)."""
+    import subprocess
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    out = {"device": pr.name, "arch": getattr(pr, "gcnArchName", None), "compute_units": pr.multi_processor_count,
+           "memory_gib": round(pr.total_memory / 2 ** 30, 1), "hip": torch.version.hip, "clocks": None}
+    def smi(flag, key):
+        try:
+            r = subprocess.run(["rocm-smi", flag], capture_output=True, text=True, timeout=20)
+        except (OSError, subprocess.SubprocessError):
+            return None
+        lines = [ln.split(":", 1)[-1].strip() for ln in r.stdout.splitlines()
+                 if "GPU[0]" in ln and key in ln.lower()]
+        return lines or None
+    out["clocks"] = smi("--showclocks", "clock level")
+    prod = smi("--showproductname", "card series")
+    out["product"] = prod[0].split(":", 1)[-1].strip() if prod else None
+    return out
 
 
 def oracle_one_core(p):
@@ -367,6 +392,7 @@ def ensemble(args):
                       "particles": N, "tile": tile, "lanes_per_particle": lpp, "persistent_grid": persist,
                       "graph_steps": 10},
            "value_by_persistent_grid": by_grid,
+           "platform": platform(),
            "hbm_frac_algorithmic": value * sum(BYTES_PER_PARTICLE.values()) / HBM_PEAK}
     sim.close()
     print(json.dumps(out), flush=True)
