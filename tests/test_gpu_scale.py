@@ -1,7 +1,8 @@
 """Parity at the benchmark's full size (2048 x 2048 box, 4,194,304 particles, the
-launch configuration bench.py times) and statistics parity on a 256 x 256 box
-over a longer horizon (kinetic energy, defect density and spectrum slope within
-2%)."""
+launch configuration bench.py times), at four times that size through the
+periodic extension of a box the oracle checks, and statistics parity on a
+256 x 256 box over a longer horizon (kinetic energy, defect density and
+spectrum slope within 2%)."""
 import os
 import sys
 
@@ -13,7 +14,7 @@ from oracle import diag
 import workloads as wl
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import check_increments, field_errors, gpu_run, run_oracle  # noqa: E402
+from gpu_common import check_increments, field_errors, gpu_run, random_state, run_oracle  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +47,55 @@ def test_full_size_ten_steps():
         assert e[k] <= 1e-5, (k, e[k])
     check_increments(e)
     sim.close()
+
+
+def test_periodic_extension_at_16m_particles():
+    """A 4096 x 4096 box (16,777,216 particles) holding 16 x 16 copies of a
+    jittered 256 x 256 box is that box's periodic extension: with the same cell
+    side (4.0), tiles aligned with the copies, the same order of particles
+    inside each cell (ascending id is the same lexicographic lattice order in
+    both) and the same global maximum speed, every particle sums the same terms
+    in the same order, so 10 steps must give each copy the small box's fields
+    bit for bit, positions shifted by the copy's offset (to the rounding of
+    their FP64 reconstruction at the larger magnitude). The small box
+    itself is checked against the oracle over the same 10 steps."""
+    side, reps = 256, 16
+    big = side * reps
+    p = wl.Params(L=float(side), zeta=0.03, K=0.04)
+    pb = p.replace(L=float(big))
+    s0 = random_state(side, 11, amp_u=2e-3)
+    print("oracle, small box", flush=True)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    sim.close()
+    e = field_errors(g, o, s0, p.L, 10)
+    print({k: f"{v:.3e}" for k, v in e.items()}, flush=True)
+    for k in ("u", "Q", "rho", "pos"):
+        assert e[k] <= 1e-5, (k, e[k])
+    check_increments(e)
+
+    def tile(a):
+        return np.tile(np.asarray(a).reshape(side, side), (reps, reps)).ravel()
+    I, J = np.meshgrid(np.arange(big), np.arange(big))        # big lattice index, x fastest
+    shift_x = (side * (I // side)).ravel().astype(np.float64)
+    shift_y = (side * (J // side)).ravel().astype(np.float64)
+    del I, J
+    sb = {k: tile(v) for k, v in s0.items()}
+    sb["x"] = sb["x"] + shift_x
+    sb["y"] = sb["y"] + shift_y
+    print("gpu, big box", big * big, flush=True)
+    gb, simb = gpu_run(pb, sb, 10)
+    simb.close()
+    del sb
+    for k in ("ux", "uy", "qxx", "qxy", "rho", "ax", "ay"):
+        if k in g:
+            assert np.array_equal(gb[k], tile(g[k])), k
+    # positions are returned as FP64 cell origin + FP32 offsets, rounded at the
+    # big box's magnitude: equal to the shifted small-box positions to a few ulp
+    for k, sh in (("x", shift_x), ("y", shift_y)):
+        d = np.mod(gb[k] - (tile(g[k]) + sh) + 0.5 * big, float(big)) - 0.5 * big
+        print(k, "largest difference", float(np.abs(d).max()), flush=True)
+        assert np.abs(d).max() < 1e-9, k
 
 
 def test_statistics_256_box():
