@@ -190,6 +190,7 @@ def main():
                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
 
+    plat = platform()   # right after the GPU work, while the clocks are at their working level
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -235,7 +236,7 @@ def main():
         "flop_per_particle_step": flops_step,
         "kernel_ms": avg,
         "cpu_baseline": cpu,
-        "platform": platform(),
+        "platform": plat,
     }
     sim.close()
     if args.calib_copy_mib:
@@ -250,8 +251,9 @@ def main():
 
 def platform():
     """The device, its architecture and compute units, the HIP version torch
-    was built with, and the clocks rocm-smi reports (current levels at the end
-    of the run; None where a query is not available)."""
+    was built with, and what rocm-smi reports: the product name and the current
+    clock levels (taken right after the timed work; None where a query is not
+    available)."""
     import subprocess
     import torch
     pr = torch.cuda.get_device_properties(0)
@@ -266,8 +268,8 @@ def platform():
                  if "GPU[0]" in ln and key in ln.lower()]
         return lines or None
     out["clocks"] = smi("--showclocks", "clock level")
-    prod = smi("--showproductname", "card series")
-    out["product"] = prod[0].split(":", 1)[-1].strip() if prod else None
+    prod = [" ".join(v.split()) for v in (smi("--showproductname", "card") or [])]
+    out["product"] = [v for v in prod if not v.upper().endswith("N/A")] or None
     return out
 
 
@@ -378,6 +380,7 @@ def ensemble(args):
         return N * args.steps / float(np.median(out)), out
 
     value, rep_s = median_value()
+    plat = platform()
     by_grid = {}
     for g in (0, 1024):
         sim.set_option(P.NEM_OPT_PERSIST, g)
@@ -392,7 +395,7 @@ def ensemble(args):
                       "particles": N, "tile": tile, "lanes_per_particle": lpp, "persistent_grid": persist,
                       "graph_steps": 10},
            "value_by_persistent_grid": by_grid,
-           "platform": platform(),
+           "platform": plat,
            "hbm_frac_algorithmic": value * sum(BYTES_PER_PARTICLE.values()) / HBM_PEAK}
     sim.close()
     print(json.dumps(out), flush=True)
