@@ -139,6 +139,30 @@ int nem_step(nem_sim* s, int64_t nsteps);
 /* Wait for the stream; return the first sticky device error (and clear nothing). */
 int nem_sync(nem_sim* s);
 
+/* Checkpoints of the whole simulation (every replica) between steps, for
+ * resuming a run bit for bit: continuing from a loaded checkpoint gives
+ * exactly the fields the saved simulation would have produced (nem_get_state
+ * and nem_set_state go through FP64 fields at the integer time level and
+ * restart the Verlet list, which is close to but not bitwise that). The
+ * checkpoint holds the device state the next step reads (current offsets and
+ * their low parts, u^{n+1/2}, Q, a^{n-1/2}, rho - rho0, ids, cells, image
+ * counters, cell starts, the max-speed slots, the status and request flags,
+ * the Verlet list), the step parity and the tile, lanes-per-particle and
+ * compensation options, and each replica's particle count and parameters.
+ *   nem_raw_bytes: the checkpoint's size in bytes (about 280 per particle).
+ *   nem_save_raw: waits for the stream and copies the checkpoint into the
+ *     caller's host buffer of `bytes` bytes (NEM_E_NOMEM if it is smaller than
+ *     nem_raw_bytes; NEM_E_STATE before every replica has a state).
+ *   nem_load_raw: loads a checkpoint into a simulation created with the same
+ *     replica count, particle counts and parameters (compared field by field;
+ *     NEM_E_INVAL when anything differs or the buffer is not a checkpoint,
+ *     NEM_E_NOMEM when it is shorter than the checkpoint; the simulation is
+ *     unchanged in those cases). It sets the saved options and drops captured
+ *     graphs. The buffer is the caller's and is only read. */
+int nem_raw_bytes(nem_sim* s, uint64_t* bytes);
+int nem_save_raw(nem_sim* s, void* host, uint64_t bytes);
+int nem_load_raw(nem_sim* s, const void* host, uint64_t bytes);
+
 /* Neighbour lists of replica r as the next step's pair passes walk them, at
  * the configuration that step uses (r^{n+1/2}), in CSR by particle id with
  * ascending columns (Eq. quintic: neighbours are the particles within the

@@ -45,7 +45,8 @@ EXPORTED = ("nem_version", "nem_arena_bytes", "nem_create", "nem_set_state", "ne
             "nem_mlp_get_norm", "nem_mlp_fit_norm", "nem_mlp_forward", "nem_mlp_grad", "nem_mlp_train",
             "nem_mlp_destroy", "nem_samples", "nem_step_learned", "nem_autotune", "nem_vorticity_correlation",
             "nem_track", "nem_mixing", "nem_set_qyy", "nem_get_qyy", "nem_neighbor_list",
-            "nem_defects_noalloc", "nem_get_option", "nem_mlp_eval", "nem_mlp_mask_outputs", "nem_samples_rows")
+            "nem_defects_noalloc", "nem_get_option", "nem_mlp_eval", "nem_mlp_mask_outputs", "nem_samples_rows",
+            "nem_raw_bytes", "nem_save_raw", "nem_load_raw")
 
 
 class NemParams(C.Structure):
@@ -96,6 +97,12 @@ def lib(path: Optional[str] = None):
     L.nem_step.argtypes = [vp, C.c_int64]
     L.nem_sync.restype = C.c_int
     L.nem_sync.argtypes = [vp]
+    L.nem_raw_bytes.restype = C.c_int
+    L.nem_raw_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
+    L.nem_save_raw.restype = C.c_int
+    L.nem_save_raw.argtypes = [vp, vp, C.c_uint64]
+    L.nem_load_raw.restype = C.c_int
+    L.nem_load_raw.argtypes = [vp, vp, C.c_uint64]
     L.nem_neighbors.restype = C.c_int
     L.nem_neighbors.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int64,
                                 C.POINTER(C.c_int64)]
@@ -345,6 +352,19 @@ def nem_mixing(h, r, colour, ncol, B):
 
 def nem_set_option(h, key: int, value: int):
     _check(h, lib().nem_set_option(C.c_void_p(h), key, int(value)), "nem_set_option")
+
+
+def nem_save_raw(h) -> np.ndarray:
+    nb = C.c_uint64(0)
+    _check(h, lib().nem_raw_bytes(C.c_void_p(h), C.byref(nb)), "nem_raw_bytes")
+    buf = np.empty(nb.value, dtype=np.uint8)
+    _check(h, lib().nem_save_raw(C.c_void_p(h), buf.ctypes.data_as(C.c_void_p), nb.value), "nem_save_raw")
+    return buf
+
+
+def nem_load_raw(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(h, lib().nem_load_raw(C.c_void_p(h), buf.ctypes.data_as(C.c_void_p), buf.size), "nem_load_raw")
 
 
 def nem_get_option(h, key: int) -> int:
@@ -602,6 +622,32 @@ class Sim:
 
     def set_option(self, key: int, value: int):
         nem_set_option(self.h, key, value)
+
+    def save_raw(self) -> np.ndarray:
+        """Bitwise checkpoint of every replica (bytes as a uint8 array)."""
+        return nem_save_raw(self.h)
+
+    def load_raw(self, buf):
+        """Continue from a checkpoint of a simulation with the same replicas."""
+        nem_load_raw(self.h, buf)
+
+    def checkpoint(self, path: str):
+        """Write the bitwise checkpoint to a file."""
+        self.save_raw().tofile(path)
+
+    def restore(self, path: str):
+        """Load a checkpoint file written by checkpoint()."""
+        self.load_raw(np.fromfile(path, dtype=np.uint8))
+
+    def save_fields(self, path: str):
+        """Every replica's fields at the integer time level (FP64, particle-id
+        order) in one .npz archive, keys '<field>_<replica>': a portable record
+        that set_state can start from (not bitwise: see checkpoint)."""
+        out = {}
+        for r in range(len(self.n)):
+            for k, v in self.get_state(r).items():
+                out[f"{k}_{r}"] = v
+        np.savez(path, **out)
 
     def get_option(self, key: int) -> int:
         return nem_get_option(self.h, key)

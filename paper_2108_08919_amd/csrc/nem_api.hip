@@ -670,6 +670,139 @@ int nem_sync(nem_sim* s) {
   return status_from_flags(s, f[0]);
 }
 
+// ------------------------------------------------------------ checkpoints
+// Whole-simulation checkpoint: a header (sizes, launch options, step parity and
+// every replica's particle count and parameters, field by field), then the
+// device state between steps in a fixed order: the current offsets, their low
+// parts, u^{n+1/2}, the current Q (and Qyy), a^{n-1/2}, rho - rho0, ids, cells,
+// image counters, cell starts, both parities' max-speed slots, the four flag
+// words, and the Verlet list with its counts and build offsets. Everything a
+// step reads before writing it is there, so a load continues bit for bit.
+namespace {
+constexpr char RAW_MAGIC[8] = {'N', 'E', 'M', 'R', 'A', 'W', '0', '1'};
+constexpr int RAW_PD = 17, RAW_PI = 7;  // doubles and integers of nem_params
+
+struct RawSeg { void* dev; size_t bytes; };
+
+std::vector<RawSeg> raw_segments(nem_sim* s) {
+  const size_t N = (size_t)s->ntot, C = (size_t)s->ncells;
+  const int p = s->parity;
+  return {{s->off[p], sizeof(float2) * N}, {s->offlo, sizeof(float2) * N}, {s->u, sizeof(float2) * N},
+          {s->q[p], sizeof(float2) * N}, {s->qyy[p], sizeof(float) * N}, {s->acc, sizeof(float2) * N},
+          {s->drho, sizeof(float) * N}, {s->id, sizeof(int) * N}, {s->cell, sizeof(int) * N},
+          {s->img, sizeof(int2) * N}, {s->cell_start, sizeof(int) * (C + 1)},
+          {s->umax, sizeof(unsigned) * 2 * (size_t)s->R * UMAX_SLOTS}, {s->flags, sizeof(unsigned) * 4},
+          {s->vl, sizeof(uint32_t) * (KMAX / 2) * N}, {s->vcnt, sizeof(int) * N},
+          {s->off_build, sizeof(float2) * N}};
+}
+
+void params_fields(const nem_params& q, double* d, int64_t* i) {
+  const double dv[RAW_PD] = {q.L, q.dx, q.h, q.rho0, q.eta, q.Gamma, q.lam, q.A, q.B, q.C,
+                             q.K, q.zeta, q.dt, q.gamma_eos, q.beta, q.c0_factor, q.skin};
+  const int64_t iv[RAW_PI] = {q.form, q.elastic, q.apd, q.kernel, q.integrator, q.q3d, 0};
+  std::memcpy(d, dv, sizeof(dv));
+  std::memcpy(i, iv, sizeof(iv));
+}
+
+// Header: magic, then int64 words {version, R, ntot, ncells, parity, T, LPP,
+// COMP}, then per replica {n, 17 doubles, 7 int64}.
+size_t raw_header_bytes(int R) { return 8 + 8 * 8 + (size_t)R * (8 + 8 * RAW_PD + 8 * RAW_PI); }
+
+size_t raw_total(nem_sim* s) {
+  size_t t = raw_header_bytes(s->R);
+  for (const RawSeg& g : raw_segments(s)) t += g.bytes;
+  return t;
+}
+}  // namespace
+
+int nem_raw_bytes(nem_sim* s, uint64_t* bytes) {
+  if (!s || !bytes) return NEM_E_INVAL;
+  *bytes = raw_total(s);
+  return NEM_OK;
+}
+
+int nem_save_raw(nem_sim* s, void* host, uint64_t bytes) {
+  if (!s || !host) return NEM_E_INVAL;
+  for (int r = 0; r < s->R; ++r)
+    if (!s->has_state[r]) { s->err = "nem_set_state was not called for every replica"; return NEM_E_STATE; }
+  if (bytes < raw_total(s)) { s->err = "checkpoint buffer smaller than nem_raw_bytes"; return NEM_E_NOMEM; }
+  char* b = (char*)host;
+  std::memcpy(b, RAW_MAGIC, 8);
+  const int64_t hw[8] = {1, s->R, s->ntot, s->ncells, s->parity, s->T, s->LPP, s->COMP};
+  std::memcpy(b + 8, hw, sizeof(hw));
+  char* w = b + 8 + sizeof(hw);
+  for (int r = 0; r < s->R; ++r) {
+    const int64_t n = s->n[r];
+    std::memcpy(w, &n, 8);
+    params_fields(s->hp[r], (double*)(w + 8), (int64_t*)(w + 8 + 8 * RAW_PD));
+    w += 8 + 8 * RAW_PD + 8 * RAW_PI;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (const RawSeg& g : raw_segments(s)) {
+    HIPCHK(hipMemcpyAsync(w, g.dev, g.bytes, hipMemcpyDeviceToHost, s->stream));
+    w += g.bytes;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
+int nem_load_raw(nem_sim* s, const void* host, uint64_t bytes) {
+  if (!s || !host) return NEM_E_INVAL;
+  const char* b = (const char*)host;
+  auto bad = [&](const char* why) { s->err = std::string("nem_load_raw: ") + why; return NEM_E_INVAL; };
+  if (bytes < raw_header_bytes(s->R) || std::memcmp(b, RAW_MAGIC, 8) != 0) return bad("not a checkpoint of this library");
+  int64_t hw[8];
+  std::memcpy(hw, b + 8, sizeof(hw));
+  if (hw[0] != 1) return bad("unknown checkpoint version");
+  if (hw[1] != s->R || hw[2] != s->ntot || hw[3] != s->ncells) return bad("replica count or sizes differ");
+  if (!(hw[4] == 0 || hw[4] == 1) || !(hw[5] == 4 || hw[5] == 8) || !(hw[6] == 1 || hw[6] == 2 || hw[6] == 4) ||
+      hw[7] < 0 || hw[7] > 2)
+    return bad("corrupt header");
+  const char* w = b + 8 + sizeof(hw);
+  for (int r = 0; r < s->R; ++r) {
+    int64_t n;
+    std::memcpy(&n, w, 8);
+    double d[RAW_PD], dh[RAW_PD];
+    int64_t i[RAW_PI], ih[RAW_PI];
+    std::memcpy(dh, w + 8, sizeof(dh));
+    std::memcpy(ih, w + 8 + 8 * RAW_PD, sizeof(ih));
+    params_fields(s->hp[r], d, i);
+    if (n != s->n[r]) return bad("particle count of a replica differs");
+    for (int k = 0; k < RAW_PD; ++k)
+      if (std::memcmp(&d[k], &dh[k], sizeof(double)) != 0) return bad("parameters of a replica differ");
+    for (int k = 0; k < RAW_PI; ++k)
+      if (i[k] != ih[k]) return bad("parameters of a replica differ");
+    w += 8 + 8 * RAW_PD + 8 * RAW_PI;
+  }
+  // segment sizes depend on the sizes only, so the length is checked before anything changes
+  if (bytes < raw_total(s)) { s->err = "nem_load_raw: buffer shorter than the checkpoint"; return NEM_E_NOMEM; }
+  // the saved launch options and parity (the Verlet list's LDS slots follow the tile)
+  drop_graphs(s);
+  const int T = (int)hw[5];
+  s->LPP = (int)hw[6];
+  s->COMP = (int)hw[7];
+  if (T != s->T) {
+    s->T = T;
+    int rc = build_work(s);
+    if (rc) return rc;
+  }
+  s->parity = (int)hw[4];
+  for (const RawSeg& g : raw_segments(s)) {
+    HIPCHK(hipMemcpyAsync(g.dev, w, g.bytes, hipMemcpyHostToDevice, s->stream));
+    w += g.bytes;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (int r = 0; r < s->R; ++r) s->has_state[r] = 1;
+  for (auto& sn : s->snap) sn.valid = false;
+  unsigned f[2];
+  int rc = read_flags(s, f);
+  if (rc) return rc;
+  return status_from_flags(s, f[0]);
+}
+
 int nem_neighbor_list(nem_sim* s, int32_t r, int32_t which, int64_t* row_ptr, int32_t* col, int64_t cap,
                       int64_t* nnz, int32_t* cell_xy, float* off_xy) {
   if (!s || r < 0 || r >= s->R || !row_ptr || !nnz || (which != 0 && which != 1)) return NEM_E_INVAL;
