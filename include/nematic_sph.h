@@ -149,7 +149,7 @@ int nem_sync(nem_sim* s);
  * counters, cell starts, the max-speed slots, the status and request flags,
  * the Verlet list), the step parity and the tile, lanes-per-particle and
  * compensation options, and each replica's particle count and parameters.
- *   nem_raw_bytes: the checkpoint's size in bytes (about 280 per particle).
+ *   nem_raw_bytes: the checkpoint's size in bytes (about 270 per particle, 192 of them the Verlet list).
  *   nem_save_raw: waits for the stream and copies the checkpoint into the
  *     caller's host buffer of `bytes` bytes (NEM_E_NOMEM if it is smaller than
  *     nem_raw_bytes; NEM_E_STATE before every replica has a state).
