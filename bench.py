@@ -15,8 +15,10 @@ launch: the per-kernel durations come from it (its own rate is reported as
 value_with_events). For context the line also carries the median with hipGraph
 replay of 10-step chunks, and the FP64 oracle timed on the host: all cores over
 whole steps of the same box, and one core over one step of a 1024 x 1024 box of
-the same physics; and the platform (device, architecture, HIP version, clock
-levels).
+the same physics; the metric's learned part (learned_4x: the corrector trained
+and evaluated against plain dt and plain 4 dt at the 2% budget, after the
+timed region; --no-learned skips it); and the platform (device, architecture,
+HIP version, clock levels).
 """
 import argparse
 import json
@@ -82,6 +84,8 @@ def main():
                     help="smoothing kernel: the paper's quintic spline (default) or the Wendland C2 variant")
     ap.add_argument("--autotune", action="store_true", help="pick tile and lanes per particle by timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-4x dt part of the metric (train on 256^2 boxes, evaluate on 1024^2)")
     ap.add_argument("--workload", choices=("box", "ensemble", "diagnostics"), default="box",
                     help="box: the 4.2M-particle box (default); ensemble: 32 uneven replicas in one launch; "
                          "diagnostics: time each grid and Lagrangian diagnostic on the box")
@@ -191,6 +195,10 @@ def main():
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
 
     plat = platform()   # right after the GPU work, while the clocks are at their working level
+    sim.close()
+    learned4 = None
+    if args.kernel == "quintic" and args.side == 2048 and not args.no_learned:
+        learned4 = learned_part()
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -236,9 +244,9 @@ def main():
         "flop_per_particle_step": flops_step,
         "kernel_ms": avg,
         "cpu_baseline": cpu,
+        "learned_4x": learned4,
         "platform": plat,
     }
-    sim.close()
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -247,6 +255,27 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+def learned_part():
+    """The metric's second part, learned 4x dt against plain stepping at the
+    error budget: the corrector trained on 256x256 boxes (1M samples) and
+    evaluated on the 1024x1024 box, 4 seeds, t in [0, 2], against plain dt =
+    1e-3 and plain 4 dt without the network (the full record is what
+    `python -m paper_2108_08919_amd.learned --mult 4` prints)."""
+    from paper_2108_08919_amd import learned
+    r = learned.run(mult=4)
+    L, Cc = r["learned"], r["plain_coarse"]
+    return {"workload": "1024x1024 box (1,048,576 particles), zeta = K = 0.02, 4 seeds, t in [0, 2]; "
+                        "dt = 1e-3 (plain) against 4e-3 (plain coarse, learned); trained on 256x256 boxes",
+            "speedup_learned_vs_plain": r["speedup_learned_vs_plain"],
+            "speedup_coarse_vs_plain": r["speedup_coarse_vs_plain"],
+            "eps_ke": L["eps_ke"], "eps_defects": L["eps_defects"],
+            "eps_ke_coarse": Cc["eps_ke"], "eps_defects_coarse": Cc["eps_defects"],
+            "within_2pct": bool(L["eps_ke"] <= 0.02 and L["eps_defects"] <= 0.02),
+            "q_field_err": L["q_field_err"], "q_field_err_coarse": Cc["q_field_err"],
+            "u_field_err": L["u_field_err"], "u_field_err_coarse": Cc["u_field_err"],
+            "fallbacks": r["fallbacks"], "held_out_rel_mse": r["held_out_rel_mse"]}
 
 
 def platform():

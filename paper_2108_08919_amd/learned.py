@@ -273,6 +273,32 @@ def evaluate(m, tau, side=1024, seeds=(0, 1, 2, 3), t_end=2.0, t_avg=(1.0, 2.0),
     return out
 
 
+def run(mult=4, epochs=20, side=1024, seeds=4):
+    """Build the training set, train, mask, set the fallback threshold and
+    evaluate against plain stepping; returns the record main() prints."""
+    t0 = time.perf_counter()
+    X, T = training_set(mult=mult)
+    t1 = time.perf_counter()
+    _log(f"training set: {X.shape[0]} samples in {t1 - t0:.1f} s")
+    m, loss = fit(X, T, epochs=epochs)
+    t2 = time.perf_counter()
+    _log(f"trained: loss {loss:.4g}, {t2 - t1:.1f} s")
+    # held-out boxes: other seeds, same recipe, every particle
+    Xh, Th = training_set(replicas=4, mult=mult, seed=1, per_replica=None)
+    rel = held_out_errors(m, Xh, Th)
+    _log(f"held-out relative MSE per output (dQxx, dQxy, dQyy, dux, duy): {[round(v, 4) for v in rel]}")
+    masked = mask_unskilled(m, rel)
+    rel_masked = held_out_errors(m, Xh, Th)
+    tau = fallback_threshold(m, Xh)
+    _log(f"masked outputs {masked}; held-out relative MSE after masking {[round(v, 4) for v in rel_masked]}; "
+         f"tau {tau:.4g}")
+    ev = evaluate(m, tau, side=side, seeds=tuple(range(seeds)), mult=mult)
+    t3 = time.perf_counter()
+    return {"samples": int(X.shape[0]), "mult": mult, "train_loss": loss,
+            "held_out_rel_mse": rel, "masked_outputs": masked, "held_out_rel_mse_masked": rel_masked,
+            "t_samples_s": t1 - t0, "t_train_s": t2 - t1, "t_eval_s": t3 - t2, **ev}
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser()
@@ -281,28 +307,7 @@ def main():
     ap.add_argument("--seeds", type=int, default=4)
     ap.add_argument("--mult", type=int, default=4)
     args = ap.parse_args()
-    t0 = time.perf_counter()
-    X, T = training_set(mult=args.mult)
-    t1 = time.perf_counter()
-    _log(f"training set: {X.shape[0]} samples in {t1 - t0:.1f} s")
-    m, loss = fit(X, T, epochs=args.epochs)
-    t2 = time.perf_counter()
-    _log(f"trained: loss {loss:.4g}, {t2 - t1:.1f} s")
-    # held-out boxes: other seeds, same recipe, every particle
-    Xh, Th = training_set(replicas=4, mult=args.mult, seed=1, per_replica=None)
-    rel = held_out_errors(m, Xh, Th)
-    _log(f"held-out relative MSE per output (dQxx, dQxy, dQyy, dux, duy): {[round(v, 4) for v in rel]}")
-    masked = mask_unskilled(m, rel)
-    rel_masked = held_out_errors(m, Xh, Th)
-    tau = fallback_threshold(m, Xh)
-    _log(f"masked outputs {masked}; held-out relative MSE after masking {[round(v, 4) for v in rel_masked]}; "
-         f"tau {tau:.4g}")
-    ev = evaluate(m, tau, side=args.side, seeds=tuple(range(args.seeds)), mult=args.mult)
-    t3 = time.perf_counter()
-    print(json.dumps({"samples": int(X.shape[0]), "mult": args.mult, "train_loss": loss,
-                      "held_out_rel_mse": rel, "masked_outputs": masked, "held_out_rel_mse_masked": rel_masked,
-                      "t_samples_s": t1 - t0,
-                      "t_train_s": t2 - t1, "t_eval_s": t3 - t2, **ev}), flush=True)
+    print(json.dumps(run(mult=args.mult, epochs=args.epochs, side=args.side, seeds=args.seeds)), flush=True)
 
 
 if __name__ == "__main__":
