@@ -80,6 +80,22 @@ def test_random_state_ten_steps(seed, opts):
     sim.close()
 
 
+def test_full_size_ten_steps_tile8():
+    """The 2048 x 2048 box with the Wendland kernel (cells of side 2.70, 7.3
+    particles each) in the launch configuration that `bench.py --kernel
+    wendland --tile 8` times, 10 steps against the oracle."""
+    import paper_2108_08919_amd as P
+    cfg = wl.config("C4")
+    p = cfg["params"].replace(kernel=1)
+    s0 = wl.state_for(cfg, 0)
+    s0["ux"], s0["uy"] = wl.smooth_velocity(s0["x"], s0["y"], p.L, 1e-3, 7)
+    print("oracle 10 steps at 4.2M particles, Wendland", flush=True)
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10, {P.NEM_OPT_TILE: 8})
+    _check(field_errors(g, o, s0, p.L, 10))
+    sim.close()
+
+
 @pytest.mark.parametrize("form,elastic", [(1, 0), (0, 1)])
 def test_forms(form, elastic):
     L = 32
