@@ -111,6 +111,39 @@ def test_ensemble_draw_against_oracle():
     sim.close()
 
 
+def test_every_graph_replay_equals_eager_steps():
+    """A captured graph of 5 steps replayed four times, with the program's own
+    eager work between the replays (FP64 reductions, a grid deposit and defect
+    count with its counter clearing, state reads) and a synchronisation after
+    each: every replay's state equals that of the same batch stepped eagerly,
+    bit for bit."""
+    import paper_2108_08919_amd as P
+    reps = sweep(4, 5)
+    sims = []
+    for graph in (0, 5):
+        sim = P.Sim([p for p, _ in reps], [s["x"].size for _, s in reps])
+        if graph:
+            sim.set_option(P.NEM_OPT_GRAPH, graph)
+        for r, (_, s) in enumerate(reps):
+            sim.set_state(r, s)
+        sims.append(sim)
+    eager, graphed = sims
+    for k in range(4):
+        for sim in sims:
+            sim.step(5)
+            sim.check()
+        for r in range(len(reps)):
+            a, b = eager.get_state(r), graphed.get_state(r)
+            for f in a:
+                assert np.array_equal(a[f], b[f]), (k, r, f)
+        # eager work on the graphed simulation's stream between replays
+        graphed.diagnostics(0)
+        graphed.defects(1, 32)
+        graphed.check()
+    for sim in sims:
+        sim.close()
+
+
 def test_persistent_grid_equals_dispatch():
     """The same batch with one workgroup per tile and with persistent grids of
     several sizes: identical results (the work list is walked in the same
