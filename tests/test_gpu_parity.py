@@ -193,6 +193,30 @@ def test_random_state_ten_steps(seed, zeta):
     sim.close()
 
 
+@pytest.mark.parametrize("h,apd", [(4.0 / 3.0, 1), (1.2, 0)])
+def test_smoothing_length_ten_steps(h, apd):
+    """The paper's smoothing length h = 4/3 dx (Sec. 3; the workloads bind
+    1.3 dx) and a narrower 1.2 dx: cells of side 3h + skin (4.44 and 4.0 on
+    L = 40), fields against the oracle over ten steps and the walked list
+    against its predicate. At 1.2 dx the lattice's sqrt(13) pairs sit 0.006
+    outside 3h = 3.6, so the jittered state keeps many pairs at the support
+    edge, where the FP32 predicate and the oracle's FP64 test can disagree;
+    every pair sum goes to zero with W there except the artificial
+    displacement's unweighted sum of r/r^3, so that case runs without it."""
+    L = 40
+    p = wl.Params(L=float(L), h=h, zeta=0.03, K=0.04, apd=apd)
+    s0 = random_state(L, 4, amp_u=2e-3)
+    say("h", h, "10 steps")
+    o, _ = run_oracle(p, s0, 10)
+    g, sim = gpu_run(p, s0, 10)
+    e = field_errors(g, o, s0, L, 10)
+    check(e)
+    assert e["pos_abs_max"] < 5e-7
+    rp, _ = _walked_list_matches_oracle(sim, p, L)
+    say("mean neighbours", float(np.diff(rp).mean()))
+    sim.close()
+
+
 def test_smallest_box_ten_steps():
     """The smallest box the library accepts: three cells per side (L = 12,
     cell side kappa h + skin = 4), so every stencil direction reaches the
