@@ -249,22 +249,45 @@ static int cells_build(cells* c, int64_t n, const double* x, const double* y, do
 }
 static void cells_free(cells* c) { free(c->start); free(c->idx); free(c->cx); free(c->cy); }
 
+static int fp32_pair(float oix, float oiy, float ojx, float ojy, int dxc, int dyc, float csf, float R2f);
+
 /* Neighbour predicate (reading of Eq. quintic's support): j != i with
  * 0 < |r_ij| < kappa h (3h for the quintic spline, 2h for Wendland C2) under
  * the minimum-image convention. W(kappa h) = 0, so pairs at exactly kappa h
- * carry no weight either way. */
+ * carry no weight either way.
+ * search 2 takes the same decision in FP32, with the arithmetic of
+ * fp32_predicate (cells of side L/nc, nc = floor(L/(kappa h + skin)), offsets
+ * fl32(x - c cs) of this configuration): a pair decision is an integer that
+ * floating point decides, so it is taken in the precision of the FP32
+ * implementation; the pair geometry stored with it stays FP64. */
 static int build_nlist(const orc_params* p, int64_t n, const double* x, const double* y,
                        int brute, nlist* nl) {
   const double L = p->L, R = orc_kappa(p->kernel) * p->h, R2 = R * R;
+  const int f32 = p->search == 2;
   memset(nl, 0, sizeof(*nl));
   nl->n = n;
   nl->ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   if (!nl->ptr) return -3;
-  int nc = (int)floor(L / R);
-  if (nc < 3) brute = 1;
+  int nc = f32 ? (int)floor(L / (R + p->skin)) : (int)floor(L / R);
+  if (nc < 3) {
+    if (f32) return -1;
+    brute = 1;
+  }
+  if (f32) brute = 0;
   cells c;
   memset(&c, 0, sizeof(c));
   if (!brute && cells_build(&c, n, x, y, L, nc)) { cells_free(&c); return -3; }
+  float *ofx = NULL, *ofy = NULL;
+  const float csf = (float)(L / nc), R2f = (float)R2;
+  if (f32) {
+    ofx = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+    ofy = (float*)malloc(sizeof(float) * (size_t)(n + 1));
+    if (!ofx || !ofy) { free(ofx); free(ofy); cells_free(&c); return -3; }
+    for (int64_t i = 0; i < n; ++i) {
+      ofx[i] = (float)(x[i] - c.cx[i] * c.cs);
+      ofy[i] = (float)(y[i] - c.cy[i] * c.cs);
+    }
+  }
 
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1) {
@@ -273,7 +296,7 @@ static int build_nlist(const orc_params* p, int64_t n, const double* x, const do
       nl->j = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
       nl->rx = (double*)malloc(sizeof(double) * (size_t)(nnz + 1));
       nl->ry = (double*)malloc(sizeof(double) * (size_t)(nnz + 1));
-      if (!nl->j || !nl->rx || !nl->ry) { cells_free(&c); return -3; }
+      if (!nl->j || !nl->rx || !nl->ry) { free(ofx); free(ofy); cells_free(&c); return -3; }
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -298,7 +321,9 @@ static int build_nlist(const orc_params* p, int64_t n, const double* x, const do
               if (j == i) continue;
               double dx = minimg(x[i] - x[j], L), dy = minimg(y[i] - y[j], L);
               double r2 = dx * dx + dy * dy;
-              if (r2 > 0.0 && r2 < R2) {
+              const int in = f32 ? fp32_pair(ofx[i], ofy[i], ofx[j], ofy[j], ox, oy, csf, R2f)
+                                 : (r2 > 0.0 && r2 < R2);
+              if (in) {
                 if (pass) { nl->j[base + cnt] = (int32_t)j; nl->rx[base + cnt] = dx; nl->ry[base + cnt] = dy; }
                 ++cnt;
               }
@@ -309,8 +334,26 @@ static int build_nlist(const orc_params* p, int64_t n, const double* x, const do
       else sort_row(nl->j + base, nl->rx + base, nl->ry + base, cnt);
     }
   }
+  free(ofx);
+  free(ofy);
   if (!brute) cells_free(&c);
   return 0;
+}
+
+/* The FP32 pair decision of fp32_predicate below, for j in the stencil cell
+ * displaced by (dxc, dyc) from i's cell. volatile keeps every operation a
+ * separately rounded FP32 operation. */
+static int fp32_pair(float oix, float oiy, float ojx, float ojy, int dxc, int dyc, float csf, float R2f) {
+  volatile float tx = oix - ojx;
+  volatile float ty = oiy - ojy;
+  volatile float sx = (float)(-dxc) * csf;
+  volatile float sy = (float)(-dyc) * csf;
+  volatile float rx = tx + sx;
+  volatile float ry = ty + sy;
+  volatile float xx = rx * rx;
+  volatile float yy = ry * ry;
+  volatile float r2 = xx + yy;
+  return r2 > 0.0f && r2 < R2f;
 }
 
 /* FP32 predicate on cell-relative offsets, the search rule of a cell-list
@@ -332,16 +375,7 @@ static int64_t fp32_predicate(const orc_params* p, int64_t n, int nc, const int3
       int dxc = ((cx[j] - cx[i]) % nc + nc) % nc; if (dxc == nc - 1) dxc = -1;
       int dyc = ((cy[j] - cy[i]) % nc + nc) % nc; if (dyc == nc - 1) dyc = -1;
       if (dxc > 1 || dyc > 1) continue;
-      volatile float tx = ox[i] - ox[j];
-      volatile float ty = oy[i] - oy[j];
-      volatile float sx = (float)(-dxc) * csf;
-      volatile float sy = (float)(-dyc) * csf;
-      volatile float rx = tx + sx;
-      volatile float ry = ty + sy;
-      volatile float xx = rx * rx;
-      volatile float yy = ry * ry;
-      volatile float r2 = xx + yy;
-      if (r2 > 0.0f && r2 < R2f) {
+      if (fp32_pair(ox[i], oy[i], ox[j], oy[j], dxc, dyc, csf, R2f)) {
         if (nnz < cap) col[nnz] = (int32_t)j;
         ++nnz;
       }
@@ -394,7 +428,9 @@ int64_t orc_neighbors(const orc_params* p, int64_t n, const double* x, const dou
                       int32_t mode, int32_t nc, int64_t* row_ptr, int32_t* col, int64_t cap) {
   if (mode == 2) return fp32_neighbors(p, n, x, y, nc, row_ptr, col, cap);
   nlist nl;
-  int rc = build_nlist(p, n, x, y, mode == 1, &nl);
+  orc_params q = *p;
+  q.search = mode == 3 ? 2 : q.search == 2 ? 0 : q.search;   /* mode 3: the step's list under search 2 */
+  int rc = build_nlist(&q, n, x, y, mode == 1, &nl);
   if (rc) { nlist_free(&nl); return rc; }
   int64_t nnz = nl.ptr[n];
   if (nnz > cap) { nlist_free(&nl); return -2; }

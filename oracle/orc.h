@@ -24,7 +24,7 @@ typedef struct orc_params {
   int32_t form;    /* 0 corrected momentum (Eq. sphMomentum), 1 conservative pair forces */
   int32_t elastic; /* 1 adds the lambda terms of Eq. elasticstress */
   int32_t apd;     /* artificial particle displacement (Eq. APD) */
-  int32_t search;  /* 0 cell list, 1 brute force O(N^2) */
+  int32_t search;  /* 0 cell list, 1 brute force O(N^2), 2 cell list with the pair decision in FP32 */
   int32_t kernel;  /* 0 quintic spline (Eq. quintic, support 3h), 1 Wendland C2 (support 2h) */
   int32_t integrator; /* corrector: 0 kick-drift-kick, 1 midpoint (u^n + a dt, r^n + u^{n+1/2} dt) */
   int32_t q3d;     /* 0: d = 2 (2x2 Q, I/2); 1: quasi-2D 3x3 Q with the printed I/3 (needs qzz) */
@@ -64,7 +64,9 @@ void orc_molecular_field3(const orc_params* p, const double* Q, const double* la
 /* Neighbour lists in CSR by particle index, columns ascending.
  * mode 0: FP64 minimum image, cell list;  1: FP64 minimum image, brute force;
  * 2: FP32 predicate on cell-relative offsets (cells of side L/nc, nc given),
- *    brute force over adjacent cells.  Returns nnz or a negative error
+ *    brute force over adjacent cells;  3: the list the step builds with
+ *    search = 2 (cell list, the same FP32 decision, nc = floor(L/(kappa h +
+ *    skin)); nc argument unused).  Returns nnz or a negative error
  *    (-2 when cap is too small). */
 int64_t orc_neighbors(const orc_params* p, int64_t n, const double* x, const double* y,
                       int32_t mode, int32_t nc, int64_t* row_ptr, int32_t* col, int64_t cap);

@@ -98,7 +98,11 @@ def check_increments(e, dr_bar=DR_BAR):
         assert e[k] <= bar, (k, e[k], bar)
 
 
-def run_oracle(params, s0, nsteps, search=0):
+def run_oracle(params, s0, nsteps, search=2):
+    """The oracle over nsteps steps. search = 2: each pair's neighbour decision
+    in FP32 on cell-relative offsets, the library's rule (an integer decision
+    that floating point takes is taken in the same precision on both sides);
+    every other operation stays FP64."""
     st = oracle.State(s0)
     if nsteps:
         oracle.step(params, st, nsteps, search=search)

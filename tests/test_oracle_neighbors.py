@@ -71,3 +71,31 @@ def test_fp32_predicate_on_lattice_is_exact():
     rp, col = oracle.neighbors(p, x, y, 2, nc)
     ref, _ = numpy_brute(x, y, float(L), 3 * p.h)
     assert rows(rp, col) == ref
+
+
+@pytest.mark.parametrize("kernel,L,seed", [(0, 24, 1), (0, 40, 2), (1, 24, 3)])
+def test_step_list_in_fp32_equals_the_brute_force_rule(kernel, L, seed):
+    """search = 2: the list the step builds (cell list, each pair decided by
+    the FP32 rule on its own cell-relative offsets) equals the brute-force
+    application of the same rule over all pairs in adjacent cells (mode 2),
+    on jittered and uniform positions, for both kernels."""
+    p = wl.Params(L=float(L), kernel=kernel)
+    nc = int(np.floor(L / (oracle.kappa(kernel) * p.h + p.skin)))
+    for x, y in (wl.jittered_lattice(L, 1.0, 0.4, seed), wl.uniform_positions(L * L, float(L), seed)):
+        a = oracle.neighbors(p, x, y, 2, nc)
+        b = oracle.neighbors(p, x, y, 3, nc)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_fp32_decision_changes_nothing_away_from_the_support_edge():
+    """On the lattice no pair lies near 3h (the nearest lattice distances are
+    sqrt(13) = 3.61 and 4), so a step that decides pairs in FP32 (search 2)
+    equals the FP64-decided step (search 0) bit for bit over five steps."""
+    cfg = wl.config("C1")
+    s0 = wl.state_for(cfg, 0)
+    a, b = oracle.State(s0), oracle.State(s0)
+    oracle.step(cfg["params"], a, 5, search=0)
+    oracle.step(cfg["params"], b, 5, search=2)
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
