@@ -76,15 +76,16 @@ int main(void) {
   int runs = 0;
   for (int kernel = 0; kernel <= 1; ++kernel) {
     const int side = kernel == 0 ? 16 : 12;
-    for (int variant = 0; variant < 6; ++variant) {
+    for (int variant = 0; variant < 7; ++variant) {
       /* 0 plain, 1 conservative form, 2 lambda stress, 3 midpoint corrector,
-       * 4 quasi-2D Q, 5 brute-force search */
+       * 4 quasi-2D Q, 5 brute-force search, 6 FP32 pair decisions */
       orc_params p = params(side, kernel);
       if (variant == 1) p.form = 1;
       if (variant == 2) p.elastic = 1;
       if (variant == 3) p.integrator = 1;
       if (variant == 4) p.q3d = 1;
       if (variant == 5) p.search = 1;
+      if (variant == 6) p.search = 2;
       arrays a;
       fill(&a, side, p.q3d);
       orc_state s = {a.n, a.x, a.y, a.ux, a.uy, a.q, a.rho, a.ax, a.ay, a.qzz};
@@ -108,7 +109,7 @@ int main(void) {
     int64_t* rp = malloc(sizeof(int64_t) * (a.n + 1));
     int32_t* col = malloc(sizeof(int32_t) * cap);
     const int nc = (int)floor(side / (orc_kappa(kernel) * p.h + p.skin));
-    for (int mode = 0; mode <= 2; ++mode) {
+    for (int mode = 0; mode <= 3; ++mode) {
       const int64_t nnz = orc_neighbors(&p, a.n, a.x, a.y, mode, nc, rp, col, cap);
       if (nnz <= 0) fail("orc_neighbors", nnz);
     }
