@@ -92,9 +92,9 @@ DRHO_BAR = 3e-5
 DR_BAR = 1e-5
 
 
-def check_increments(e, dr_bar=DR_BAR):
+def check_increments(e):
     for k, bar in (("du_res", RES_BAR), ("dQ_res", RES_BAR), ("drho_l2", DRHO_BAR), ("drho_max", DRHO_BAR),
-                   ("dr_l2", dr_bar), ("dr_max", dr_bar)):
+                   ("dr_l2", DR_BAR), ("dr_max", DR_BAR)):
         assert e[k] <= bar, (k, e[k], bar)
 
 

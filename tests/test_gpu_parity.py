@@ -149,14 +149,14 @@ def test_state_roundtrip():
 
 # --------------------------------------------------------------- fields
 
-def check(e, tol=TOL, strict_keys=("u", "Q", "rho", "pos"), dr_bar=None):
+def check(e, tol=TOL, strict_keys=("u", "Q", "rho", "pos")):
     """Fields within tol (relative L2) and, when the run's step count was
     given, the increments within the bars of gpu_common."""
     say({k: f"{v:.3e}" for k, v in e.items()})
     for k in strict_keys:
         assert e[k] <= tol, (k, e[k])
     if "du_res" in e:
-        check_increments(e, **({} if dr_bar is None else {"dr_bar": dr_bar}))
+        check_increments(e)
 
 
 def test_c1_ten_steps():
