@@ -1,17 +1,20 @@
-"""Write the FP64 oracle's long-run statistics of the single run at scale.
+"""Write the FP64 oracle's long-run statistics of a single box.
 
-Workload: the 512 x 512 lattice box (262,144 particles, L = 512, zeta = K = 0.02,
-dt = 1e-3, isotropic director start, seed 0), 10,000 steps. Every 500 steps the
-oracle records the kinetic energy (Eq. kineticenergy as a particle average),
-the defect density ((n+ + n-)/L^2 from the director winding on the 512 x 512
-deposit grid) and the slope of the kinetic-energy spectrum over shells 4..64
-(paper Sec. 5: energy spectrum and defect maps).
+Workloads (isotropic director start, seed 0, zeta = K = 0.02, dt = 1e-3):
+  C2: the 512 x 512 lattice box (262,144 particles), 10,000 steps, a sample
+      every 500 (about an hour on 8 host cores);
+  C4: the 2048 x 2048 lattice box (4,194,304 particles), 2,000 steps, a sample
+      every 250 (about two hours on 8 host cores).
+Each sample records the kinetic energy (Eq. kineticenergy as a particle
+average), the defect density ((n+ + n-)/L^2 from the director winding on the
+side x side deposit grid) and the slope of the kinetic-energy spectrum over
+shells 4..side/8 (paper Sec. 5: energy spectrum and defect maps).
 
 Only the oracle runs here (test infrastructure: oracle/ and the seeded inputs of
 workloads/); the GPU suite compares its own run of the same workload against
-the stored series. It takes about an hour on 8 host cores:
+the stored series:
 
-    python tests/golden/make_c2_statistics.py [--steps 10000] [--every 500]
+    python tests/golden/make_c2_statistics.py [--config C2|C4] [--steps N] [--every K]
 """
 import argparse
 import json
@@ -31,11 +34,17 @@ import workloads as wl  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--every", type=int, default=500)
-    ap.add_argument("--out", default=os.path.join(HERE, "c2_512box_oracle_statistics.json"))
+    ap.add_argument("--config", choices=("C2", "C4"), default="C2")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--every", type=int, default=None)
+    ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    cfg = wl.config("C2")
+    defaults = {"C2": (10000, 500, "c2_512box_oracle_statistics.json"),
+                "C4": (2000, 250, "c4_2048box_oracle_statistics.json")}[a.config]
+    a.steps = a.steps or defaults[0]
+    a.every = a.every or defaults[1]
+    a.out = a.out or os.path.join(HERE, defaults[2])
+    cfg = wl.config(a.config)
     p, side = cfg["params"], cfg["n_side"]
     st = oracle.State(wl.state_for(cfg, 0))
     series = []
@@ -49,7 +58,7 @@ def main():
                            defects=(npl + nmi) / side ** 2, slope=slope))
         print(json.dumps(series[-1]), f"{time.perf_counter() - t0:.0f} s", flush=True)
     out = dict(
-        _source=("FP64 oracle (oracle/orc.c, oracle/diag.py) on the 512 x 512 lattice box, written by "
+        _source=(f"FP64 oracle (oracle/orc.c, oracle/diag.py) on the {side} x {side} lattice box, written by "
                  "tests/golden/make_c2_statistics.py; no value comes from the GPU path"),
         workload=dict(n_side=side, L=p.L, zeta=p.zeta, K=p.K, dt=p.dt, seed=0, kind=cfg["kind"],
                       steps=a.steps, every=a.every, spectrum_shells=[4, side // 8]),
