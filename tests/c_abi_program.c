@@ -2,7 +2,9 @@
  * device arena (arena = NULL) and works on the null stream. Reads an initial
  * state of n particles (9 arrays of doubles in id order: x y ux uy qxx qxy rho
  * ax ay) and the number of steps, advances one box, and writes the state back
- * in the same layout followed by the FP64 diagnostics.
+ * in the same layout followed by the FP64 diagnostics. Half way it saves a
+ * checkpoint, destroys the simulation and continues in a new one loaded from
+ * the checkpoint, so the output is also a test of resuming bit for bit.
  *
  *   c_abi_program <side> <steps> <state_in.bin> <state_out.bin>
  *
@@ -42,7 +44,23 @@ int main(int argc, char** argv) {
   for (int k = 0; k < 9; ++k) a[k] = f + (size_t)k * n;
   rc = nem_set_state(s, 0, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8]);
   if (rc) return fail(s, rc, "nem_set_state");
-  rc = nem_step(s, steps);
+  rc = nem_step(s, steps / 2);
+  if (rc) return fail(s, rc, "nem_step");
+  uint64_t cb = 0;
+  rc = nem_raw_bytes(s, &cb);
+  if (rc) return fail(s, rc, "nem_raw_bytes");
+  void* ckpt = malloc((size_t)cb);
+  if (!ckpt) return fail(s, NEM_E_NOMEM, "malloc");
+  rc = nem_save_raw(s, ckpt, cb);
+  if (rc) return fail(s, rc, "nem_save_raw");
+  nem_destroy(s);
+  s = NULL;
+  rc = nem_create(&p, &n, 1, NULL, 0, NULL, &s);
+  if (rc) return fail(NULL, rc, "nem_create (resume)");
+  rc = nem_load_raw(s, ckpt, cb);
+  free(ckpt);
+  if (rc) return fail(s, rc, "nem_load_raw");
+  rc = nem_step(s, steps - steps / 2);
   if (rc) return fail(s, rc, "nem_step");
   rc = nem_sync(s);
   if (rc) return fail(s, rc, "nem_sync");

@@ -1,7 +1,8 @@
 """The C ABI used from plain C: tests/c_abi_program.c (built by build() into
 tests/_bin) lets the library allocate its own device arena and use the null
-stream, advances a box 20 steps and writes the state back. It must equal, bit
-for bit, the same run through the Python binding (torch arena and stream)."""
+stream, advances a box 20 steps (10, a checkpoint into a new simulation, 10
+more) and writes the state back. It must equal, bit for bit, the same run
+through the Python binding (torch arena and stream) without the checkpoint."""
 import os
 import subprocess
 import sys
