@@ -4,7 +4,7 @@ Workloads (isotropic director start, seed 0, zeta = K = 0.02, dt = 1e-3):
   C2: the 512 x 512 lattice box (262,144 particles), 10,000 steps, a sample
       every 500 (about an hour on 8 host cores);
   C4: the 2048 x 2048 lattice box (4,194,304 particles), 2,000 steps, a sample
-      every 250 (about two hours on 8 host cores).
+      every 250 (about four and a half hours on 8 host cores).
 Each sample records the kinetic energy (Eq. kineticenergy as a particle
 average), the defect density ((n+ + n-)/L^2 from the director winding on the
 side x side deposit grid) and the slope of the kinetic-energy spectrum over
