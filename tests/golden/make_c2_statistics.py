@@ -1,12 +1,14 @@
 """Write the FP64 oracle's long-run statistics of a single box.
 
-Workloads (isotropic director start, seed 0, zeta = K = 0.02, dt = 1e-3):
+Workloads (isotropic director start, seed 0, zeta = K = 0.02 unless stated, dt = 1e-3):
   C2: the 512 x 512 lattice box (262,144 particles), 10,000 steps, a sample
       every 500 (about an hour on 8 host cores);
   C4: the 2048 x 2048 lattice box (4,194,304 particles), 2,000 steps, a sample
       every 250 (about four and a half hours on 8 host cores);
   C2W: the C2 box with the Wendland C2 kernel (support 2h, 20 lattice
-      neighbours), 5,000 steps, a sample every 500.
+      neighbours), 5,000 steps, a sample every 500;
+  C2C: the C2 box with contractile activity, zeta = -0.02, 5,000 steps, a
+      sample every 500.
 Each sample records the kinetic energy (Eq. kineticenergy as a particle
 average), the defect density ((n+ + n-)/L^2 from the director winding on the
 side x side deposit grid) and the slope of the kinetic-energy spectrum over
@@ -16,7 +18,7 @@ Only the oracle runs here (test infrastructure: oracle/ and the seeded inputs of
 workloads/); the GPU suite compares its own run of the same workload against
 the stored series:
 
-    python tests/golden/make_c2_statistics.py [--config C2|C4|C2W] [--steps N] [--every K]
+    python tests/golden/make_c2_statistics.py [--config C2|C4|C2W|C2C] [--steps N] [--every K]
 """
 import argparse
 import json
@@ -36,20 +38,24 @@ import workloads as wl  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", choices=("C2", "C4", "C2W"), default="C2")
+    ap.add_argument("--config", choices=("C2", "C4", "C2W", "C2C"), default="C2")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    defaults = {"C2": (10000, 500, "c2_512box_oracle_statistics.json"),
-                "C4": (2000, 250, "c4_2048box_oracle_statistics.json"),
-                "C2W": (5000, 500, "c2_512box_wendland_oracle_statistics.json")}[a.config]
+    # config -> (base workload, parameter changes, steps, sample interval, file)
+    base, change, steps, every, name = {
+        "C2": ("C2", {}, 10000, 500, "c2_512box_oracle_statistics.json"),
+        "C4": ("C4", {}, 2000, 250, "c4_2048box_oracle_statistics.json"),
+        "C2W": ("C2", {"kernel": 1}, 5000, 500, "c2_512box_wendland_oracle_statistics.json"),
+        "C2C": ("C2", {"zeta": -0.02}, 5000, 500, "c2_512box_contractile_oracle_statistics.json")}[a.config]
+    defaults = (steps, every, name)
     a.steps = a.steps or defaults[0]
     a.every = a.every or defaults[1]
     a.out = a.out or os.path.join(HERE, defaults[2])
-    cfg = wl.config(a.config.rstrip("W"))
-    kernel = 1 if a.config.endswith("W") else 0
-    p, side = cfg["params"].replace(kernel=kernel), cfg["n_side"]
+    cfg = wl.config(base)
+    p, side = cfg["params"].replace(**change), cfg["n_side"]
+    kernel = p.kernel
     st = oracle.State(wl.state_for(cfg, 0))
     series = []
     t0 = time.perf_counter()

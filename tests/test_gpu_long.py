@@ -5,11 +5,13 @@
   * the benchmark's 2048 x 2048 lattice box (4,194,304 particles), 2,000 steps
     sampled every 250 (c4_2048box_oracle_statistics.json);
   * the 512 x 512 box with the Wendland C2 kernel, 5,000 steps sampled every
-    500 (c2_512box_wendland_oracle_statistics.json).
-Both start isotropic (seed 0) with zeta = K = 0.02, dt = 1e-3. The GPU runs the
-same steps and records the kinetic energy, the defect density and the spectrum
-slope at the same samples; the means over the run must agree within 2%, and
-the samples are reported one by one."""
+    500 (c2_512box_wendland_oracle_statistics.json);
+  * the 512 x 512 box with contractile activity (zeta = -0.02), 5,000 steps
+    sampled every 500 (c2_512box_contractile_oracle_statistics.json).
+All start isotropic (seed 0) with zeta = K = 0.02 unless stated, dt = 1e-3.
+The GPU runs the same steps and records the kinetic energy, the defect density
+and the spectrum slope at the same samples; the means over the run must agree
+within 2%, and the samples are reported one by one."""
 import json
 import os
 import time
@@ -28,22 +30,21 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _against_series(config, name, kernel=0):
+def _against_series(config, name, make=None, **change):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2108_08919_amd as P
     path = os.path.join(GOLDEN, name)
     if not os.path.exists(path):
-        make = config + ("W" if kernel else "")
-        pytest.skip(f"{name} not written yet (python tests/golden/make_c2_statistics.py --config {make})")
+        pytest.skip(f"{name} not written yet (python tests/golden/make_c2_statistics.py --config {make or config})")
     with open(path) as fh:
         ref = json.load(fh)
     cfg = wl.config(config)
-    p, side = cfg["params"].replace(kernel=kernel), cfg["n_side"]
+    p, side = cfg["params"].replace(**change), cfg["n_side"]
     w = ref["workload"]
     assert (w["n_side"], w["L"], w["zeta"], w["K"], w["dt"], w["seed"]) == (side, p.L, p.zeta, p.K, p.dt, 0)
-    assert w.get("kernel", 0) == kernel
+    assert w.get("kernel", 0) == p.kernel
     every, n_steps = w["every"], w["steps"]
     sim = P.Sim([p], [side * side])
     sim.set_state(0, wl.state_for(cfg, 0))
@@ -81,4 +82,8 @@ def test_c4_statistics_against_oracle_series():
 
 
 def test_c2_wendland_statistics_against_oracle_series():
-    _against_series("C2", "c2_512box_wendland_oracle_statistics.json", kernel=1)
+    _against_series("C2", "c2_512box_wendland_oracle_statistics.json", make="C2W", kernel=1)
+
+
+def test_c2_contractile_statistics_against_oracle_series():
+    _against_series("C2", "c2_512box_contractile_oracle_statistics.json", make="C2C", zeta=-0.02)
