@@ -10,7 +10,9 @@ Workloads (isotropic director start, seed 0, zeta = K = 0.02 unless stated, dt =
   C2C: the C2 box with contractile activity, zeta = -0.02, 5,000 steps, a
       sample every 500;
   C2M: the C2 box with the midpoint corrector, 2,500 steps, a sample every
-      500.
+      500;
+  C2F: the C2 box with the conservative pair forces (form 1), 2,500 steps, a
+      sample every 500.
 Each sample records the kinetic energy (Eq. kineticenergy as a particle
 average), the defect density ((n+ + n-)/L^2 from the director winding on the
 side x side deposit grid) and the slope of the kinetic-energy spectrum over
@@ -20,7 +22,7 @@ Only the oracle runs here (test infrastructure: oracle/ and the seeded inputs of
 workloads/); the GPU suite compares its own run of the same workload against
 the stored series:
 
-    python tests/golden/make_c2_statistics.py [--config C2|C4|C2W|C2C|C2M] [--steps N] [--every K]
+    python tests/golden/make_c2_statistics.py [--config C2|C4|C2W|C2C|C2M|C2F] [--steps N] [--every K]
 """
 import argparse
 import json
@@ -40,7 +42,7 @@ import workloads as wl  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", choices=("C2", "C4", "C2W", "C2C", "C2M"), default="C2")
+    ap.add_argument("--config", choices=("C2", "C4", "C2W", "C2C", "C2M", "C2F"), default="C2")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--out", default=None)
@@ -51,7 +53,8 @@ def main():
         "C4": ("C4", {}, 2000, 250, "c4_2048box_oracle_statistics.json"),
         "C2W": ("C2", {"kernel": 1}, 5000, 500, "c2_512box_wendland_oracle_statistics.json"),
         "C2C": ("C2", {"zeta": -0.02}, 5000, 500, "c2_512box_contractile_oracle_statistics.json"),
-        "C2M": ("C2", {"integrator": 1}, 2500, 500, "c2_512box_midpoint_oracle_statistics.json")}[a.config]
+        "C2M": ("C2", {"integrator": 1}, 2500, 500, "c2_512box_midpoint_oracle_statistics.json"),
+        "C2F": ("C2", {"form": 1}, 2500, 500, "c2_512box_form1_oracle_statistics.json")}[a.config]
     defaults = (steps, every, name)
     a.steps = a.steps or defaults[0]
     a.every = a.every or defaults[1]
@@ -74,7 +77,7 @@ def main():
         _source=(f"FP64 oracle (oracle/orc.c, oracle/diag.py) on the {side} x {side} lattice box, written by "
                  "tests/golden/make_c2_statistics.py; no value comes from the GPU path"),
         workload=dict(n_side=side, L=p.L, zeta=p.zeta, K=p.K, dt=p.dt, seed=0, kind=cfg["kind"], kernel=kernel,
-                      integrator=p.integrator,
+                      integrator=p.integrator, form=p.form,
                       steps=a.steps, every=a.every, spectrum_shells=[4, side // 8]),
         threads=oracle.num_threads(), seconds=time.perf_counter() - t0, series=series)
     with open(a.out, "w") as fh:

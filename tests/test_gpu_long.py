@@ -9,7 +9,9 @@
   * the 512 x 512 box with contractile activity (zeta = -0.02), 5,000 steps
     sampled every 500 (c2_512box_contractile_oracle_statistics.json);
   * the 512 x 512 box with the midpoint corrector, 2,500 steps sampled every
-    500 (c2_512box_midpoint_oracle_statistics.json).
+    500 (c2_512box_midpoint_oracle_statistics.json);
+  * the 512 x 512 box with the conservative pair forces (form 1), 2,500 steps
+    sampled every 500 (c2_512box_form1_oracle_statistics.json).
 All start isotropic (seed 0) with zeta = K = 0.02 unless stated, dt = 1e-3.
 The GPU runs the same steps and records the kinetic energy, the defect density
 and the spectrum slope at the same samples; the means over the run must agree
@@ -47,6 +49,7 @@ def _against_series(config, name, make=None, **change):
     w = ref["workload"]
     assert (w["n_side"], w["L"], w["zeta"], w["K"], w["dt"], w["seed"]) == (side, p.L, p.zeta, p.K, p.dt, 0)
     assert w.get("kernel", 0) == p.kernel and w.get("integrator", 0) == p.integrator
+    assert w.get("form", 0) == p.form
     every, n_steps = w["every"], w["steps"]
     sim = P.Sim([p], [side * side])
     sim.set_state(0, wl.state_for(cfg, 0))
@@ -93,3 +96,7 @@ def test_c2_contractile_statistics_against_oracle_series():
 
 def test_c2_midpoint_statistics_against_oracle_series():
     _against_series("C2", "c2_512box_midpoint_oracle_statistics.json", make="C2M", integrator=1)
+
+
+def test_c2_form1_statistics_against_oracle_series():
+    _against_series("C2", "c2_512box_form1_oracle_statistics.json", make="C2F", form=1)
